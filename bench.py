@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the voxel-parallel fitting hot path on one MI355X.
+
+Headline (``value``): Metropolis-Hastings voxel-chain-iterations per second
+on the 3-pool complex GRE workload (128 x 128 x 64 voxels, 24 echoes,
+4 chains x 5,000 iterations, burn-in 500, thinning 100, FP32 chains with
+FP64 moments).  One step = one gc_mcmc call over the whole volume with the
+data already resident in HBM (pack -> init -> fused MH chunks -> moment
+merge -> scatter to grid maps).
+
+Second leg (``adam``): the whole-volume Adam fit with 3D TV on the stick +
+ball diffusion workload (64^3 voxels, 96 measurements, 500 iterations,
+lambda 1e-3 on f, Da, De), voxel-iterations per second.
+
+Each leg reports a roofline entry for its dominant kernel: algorithmic
+FLOPs (MH, ALU bound) or bytes (Adam+TV step, HBM bound) per launch divided
+by the launch time measured with HIP events on the launch stream.  The CPU
+baseline times the FP64 oracle (all host threads) on a bounded voxel sample
+of the MH workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 operations of one gre3 MH step with the echo recurrence
+# (add / mul = 1, FMA = 2, transcendental = 1):
+#   proposal 9 x FMA                                   18
+#   Box-Muller 5 pairs x (log, mul, sqrt, sin, cos, 2 mul)   35
+#   acceptance log, subtract                            2
+#   per pool set-up: rcp, 2 x (2 mul, exp, sin, cos, 2 mul), amplitude 2 mul   3 x 17 = 51
+#   per echo: 3 complex updates (4 mul + 2 add) + 4 adds + 2 sub + 2 FMA: 28 x 24 = 672
+#   likelihood scale                                    1
+FLOP_PER_MH_STEP_GRE3 = 18 + 35 + 2 + 51 + 672 + 1      # = 779
+# Algorithmic HBM bytes per voxel-iteration of the dwi2 Adam+TV step kernel:
+#   data 96 x 4, iterate 5 x 4 in + out, Adam m, v 2 x 5 x 4 in + out,
+#   neighbour table 6 x 4 (neighbour iterate values are re-reads of the
+#   iterate and are not counted again)
+BYTES_PER_ADAM_TV_VOXEL_ITER = 96 * 4 + 2 * 5 * 4 + 2 * 2 * 5 * 4 + 6 * 4   # = 528
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mh_leg(g, torch, steps, warmup):
+    from paper_2511_22094_amd import synth
+    d = synth.cfg1()
+    kw = synth.CFG1_MCMC
+    m = g.Model.from_acq("gre3", d.acq)
+    dev = torch.device("cuda:0")
+    nz, ny, nx = d.shape
+    truth = torch.tensor(d.truth, dtype=torch.float32, device=dev)
+    s = g.gc_model_forward(m, truth)
+    y = (s + d.sigma * torch.from_numpy(d.noise).to(dev)).reshape(48, nz, ny, nx).contiguous()
+    del s, truth
+    step = synth.MH_STEP["gre3"]
+    mean = torch.empty((9, nz, ny, nx), dtype=torch.float64, device=dev)
+    std = torch.empty_like(mean)
+
+    def run():
+        return g.gc_mcmc(m, y, None, d.lb, d.ub, sigma=d.sigma, step=step, seed=1,
+                         accept=False, out_mean=mean, out_std=std, **kw)
+
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    g.gc_timing_reset()
+    g.gc_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.gc_timing_enable(False)
+    kms, nl = g.gc_timing_get("mh_chunk")
+    n = d.n
+    units = n * kw["n_chains"] * kw["n_iter"]
+    sec = (t1 - t0) / steps
+    per_launch_s = kms / 1e3 / max(nl, 1)
+    launches_per_step = nl / steps
+    units_per_launch = units / launches_per_step
+    achieved = FLOP_PER_MH_STEP_GRE3 * units_per_launch / per_launch_s / 1e12
+    finite = bool(torch.isfinite(mean).all().item())
+    return dict(units=units, sec=sec, value=units / sec, per_launch_ms=per_launch_s * 1e3,
+                launches=launches_per_step, achieved_tflops=achieved, finite=finite,
+                n=n, workload=d)
+
+
+def adam_leg(g, torch, steps, warmup):
+    from paper_2511_22094_amd import synth
+    d = synth.cfg2()
+    kw = synth.CFG2_ADAM
+    m = g.Model.from_acq("dwi2", d.acq)
+    dev = torch.device("cuda:0")
+    nz, ny, nx = d.shape
+    truth = torch.tensor(d.truth, dtype=torch.float32, device=dev)
+    s = g.gc_model_forward(m, truth)
+    y = (s + d.sigma * torch.from_numpy(d.noise).to(dev)).reshape(96, nz, ny, nx).contiguous()
+    out = torch.empty((5, nz, ny, nx), dtype=torch.float32, device=dev)
+    mask = torch.from_numpy(d.mask).to(dev)
+    tvp = tuple(synth.PARAM_NAMES["dwi2"].index(p) for p in kw["tv_params"])
+
+    def run():
+        return g.gc_fit_askadam(m, y, mask, d.lb, d.ub, n_iter=kw["n_iter"], loss=kw["loss"],
+                                lam=kw["lam"], tv_params=tvp, tv_dim=kw["tv_dim"], out=out)
+
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    g.gc_timing_reset()
+    g.gc_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.gc_timing_enable(False)
+    kms, nl = g.gc_timing_get("fit_step")
+    n = d.n
+    units = n * kw["n_iter"]
+    sec = (t1 - t0) / steps
+    per_launch_s = kms / 1e3 / max(nl, 1)
+    gbs = BYTES_PER_ADAM_TV_VOXEL_ITER * n / per_launch_s / 1e9
+    return dict(units=units, sec=sec, value=units / sec, per_launch_us=per_launch_s * 1e6,
+                achieved_gbs=gbs, final_loss=r["final_loss"], n=n)
+
+
+def cpu_baseline(sample_vox=384):
+    """The FP64 oracle on a fixed voxel sample of the MH workload, all host threads."""
+    import oracle
+    from paper_2511_22094_amd import synth
+    d = synth.cfg1()
+    kw = synth.CFG1_MCMC
+    rng = np.random.default_rng(1234)
+    idx = np.sort(rng.choice(d.n, sample_vox, replace=False))
+    y = (oracle.forward("gre3", d.acq, d.truth[:, idx]) + d.sigma * d.noise[:, idx]).astype(np.float32)
+    threads = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    oracle.mh("gre3", d.acq, y, d.lb, d.ub, synth.MH_STEP["gre3"], d.sigma, 1, vidx=idx,
+              n_threads=threads, **kw)
+    sec = time.perf_counter() - t0
+    units = sample_vox * kw["n_chains"] * kw["n_iter"]
+    return dict(value=units / sec, unit="voxel-iterations/s", cores=threads, kind="oracle",
+                sample=f"{sample_vox} random voxels of the 128x128x64 gre3 volume, "
+                       f"{kw['n_chains']} chains x {kw['n_iter']} iterations, "
+                       f"FP64, {sec:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-adam", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2511_22094_amd import lib
+    g = lib()
+    log("bench: MH leg (gre3 128x128x64, 4 chains x 5000)")
+    mh = mh_leg(g, torch, args.steps, args.warmup)
+    log(f"bench: MH {mh['value']:.3e} voxel-iter/s, {mh['sec']:.3f} s/step, "
+        f"kernel {mh['per_launch_ms']:.2f} ms/launch")
+    adam = None
+    if not args.no_adam:
+        log("bench: Adam+TV leg (dwi2 64^3, 500 iterations)")
+        adam = adam_leg(g, torch, args.steps, args.warmup)
+        log(f"bench: Adam {adam['value']:.3e} voxel-iter/s, step kernel "
+            f"{adam['per_launch_us']:.1f} us")
+    cpu = None
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        cpu = cpu_baseline()
+        log(f"bench: CPU {cpu['value']:.3e} voxel-iter/s on {cpu['cores']} threads")
+    out = {
+        "metric": "voxel-iterations/sec (MCMC MH & Adam steps) at 1 GPU",
+        "value": mh["value"],
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mh["sec"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gre3 3-pool complex GRE MCMC, 128x128x64 voxels, 24 echoes, "
+                               "4 chains x 5000 iters, burn-in 500, thin 100, FP64 moments",
+                   "voxels": mh["n"], "chains": 4, "iterations": 5000},
+        "roofline": {"bound": "alu", "kernel": "mh_chunk<gre3,f32,24>",
+                     "achieved": mh["achieved_tflops"], "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": mh["achieved_tflops"] / PEAK_FP32_TFLOPS,
+                     "traffic": None, "flop_per_step": FLOP_PER_MH_STEP_GRE3,
+                     "launch_ms": mh["per_launch_ms"]},
+        "cpu_baseline": cpu,
+    }
+    if adam is not None:
+        out["adam"] = {"value": adam["value"], "unit": "voxel-iterations/s",
+                       "ms_per_step": adam["sec"] * 1e3,
+                       "workload": "dwi2 stick+ball, 64^3 voxels, 96 measurements, Adam 500 "
+                                   "iterations, 3D TV lambda 1e-3 on f, Da, De",
+                       "roofline": {"bound": "hbm", "kernel": "fit_step<dwi2>",
+                                    "achieved": adam["achieved_gbs"], "peak": PEAK_HBM_GBS,
+                                    "unit": "GB/s", "frac": adam["achieved_gbs"] / PEAK_HBM_GBS,
+                                    "traffic": None,
+                                    "bytes_per_voxel_iter": BYTES_PER_ADAM_TV_VOXEL_ITER,
+                                    "launch_us": adam["per_launch_us"]}}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -65,6 +65,8 @@ def lib():
         L.orc_mh.argtypes = [i32, i32, P, P, P, i64, P, P, P, P, P, P, P, dbl, u64,
                              i32, i32, i32, i32, P, P, P, P, P, P, P, i32]
         L.orc_logl.argtypes = [i32, i32, P, P, P, P, P, P, i64, dbl, P]
+        L.orc_ensemble.argtypes = [i32, i32, P, P, P, i64, P, P, P, P, P, P, i32, dbl, u64,
+                                   i32, dbl, i32, i32, i32, P, P, P, P, P, i32]
         _lib = L
     return _lib
 
@@ -279,3 +281,34 @@ def mh(model: str, acq, y, lb, ub, step, sigma, seed, n_chains, n_iter, burnin, 
     assert rc == 0, rc
     return dict(mean=mean, std=sd, accept=acc, final=fin, logl=fll, margin=marg,
                 samples=samples)
+
+
+def ensemble(model: str, acq, y, lb, ub, sigma, seed, n_walkers, n_iter, burnin, thin,
+             stretch=2.0, x0=None, x0_mode=0, w=None, vidx=None, keep_samples=False,
+             n_threads=0):
+    """Affine-invariant ensemble sampler on compacted voxels y[Meff, n];
+    x0 [P, n] (default midpoint) is the centre of the starting ball.
+
+    Returns dict(mean, std [P,n], accept [K,n], final [P,K,n], samples [K,S,P,n])."""
+    a = Acq.of(acq)
+    y = _f32(y)
+    n = y.shape[1]
+    P = NPARAMS[model]
+    lb, ub = _f64(lb), _f64(ub)
+    if x0 is None:
+        x0 = np.broadcast_to((0.5 * (lb + ub))[:, None], (P, n))
+    x0 = _f64(x0)
+    w = _f32(w)
+    vidx = np.ascontiguousarray(np.arange(n) if vidx is None else vidx, dtype=np.uint32)
+    S = mh_nkeep(n_iter, burnin, thin)
+    samples = np.zeros((n_walkers, S, P, n)) if keep_samples else None
+    mean = np.zeros((P, n))
+    sd = np.zeros((P, n))
+    acc = np.zeros((n_walkers, n), dtype=np.int32)
+    fin = np.zeros((P, n_walkers, n))
+    rc = lib().orc_ensemble(MODEL_IDS[model], *a.args(), n, _p(y), _p(w), _p(vidx), _p(lb),
+                            _p(ub), _p(x0), x0_mode, sigma, ctypes.c_uint64(seed), n_walkers,
+                            stretch, n_iter, burnin, thin, _p(samples), _p(mean), _p(sd),
+                            _p(acc), _p(fin), n_threads)
+    assert rc == 0, rc
+    return dict(mean=mean, std=sd, accept=acc, final=fin, samples=samples)

@@ -684,3 +684,126 @@ int orc_logl(int model, int M, const double *te, const double *bval, const doubl
     free(s);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Affine-invariant ensemble sampler (paper §2.2.2; Goodman & Weare 2010).
+ *
+ * K walkers per voxel split into halves S0 = {0..K/2-1}, S1 = {K/2..K-1};
+ * iteration t updates S0 against S1, then S1 against the updated S0 (the
+ * parallel form of the stretch move).  For walker k of half h the counter
+ * (v, k | 2 << 16, t, 0) gives word 0 -> partner j = (other half start) +
+ * floor(u0 K/2), word 1 -> z = ((a-1) u1 + 1)^2 / a (density ~ 1/sqrt(z) on
+ * [1/a, a]), word 2 -> acceptance uniform; Y = X_j + z (X_k - X_j); outside
+ * the box -> reject; accept iff log u2 < (P-1) log z + logL(Y) - logL(X_k).
+ * Walkers start at x0 plus 1 % of the box width times a standard normal
+ * (counter (v, k | 1 << 16, 0, b), Box-Muller on word pairs), clamped to the
+ * box; x0_mode 1 starts them uniformly in the box.  Retention and moments
+ * as for MH, with walkers in place of chains.
+ * ------------------------------------------------------------------------ */
+int orc_ensemble(int model, int M, const double *te, const double *bval, const double *bvec,
+                 int64_t n, const float *y, const float *w, const uint32_t *vidx,
+                 const double *lb, const double *ub, const double *x0 /*[P][n]*/, int x0_mode,
+                 double sigma, uint64_t seed, int K, double a, int n_iter, int burnin, int thin,
+                 double *samples /*[K][S][P][n] or NULL*/, double *mean, double *sd,
+                 int32_t *accept /*[K][n]*/, double *final_state /*[P][K][n]*/, int n_threads) {
+    orc_model m;
+    if (make_model(&m, model, M, te, bval, bvec)) return -1;
+    if (K < 4 || K % 2) return -2;
+    int P = m.P, hp = K / 2;
+    int64_t S = orc_mh_nkeep(n_iter, burnin, thin);
+    double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel
+    {
+        double *X = (double *)malloc(sizeof(double) * K * P);
+        double *lp = (double *)malloc(sizeof(double) * K);
+        int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * K);
+        double *keep = (double *)malloc(sizeof(double) * ((size_t)K * S + 1) * P);
+        double *s = (double *)malloc(sizeof(double) * m.Meff);
+        double Y[16];
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < n; ++i) {
+            uint32_t v = vidx[i];
+            double wi = w ? (double)w[i] : 1.0;
+            for (int k = 0; k < K; ++k) {
+                if (x0_mode == 1) {
+                    orc_init_uniform(seed, v, (uint32_t)k, P, lb, ub, X + k * P);
+                } else {
+                    for (int b = 0; b < (P + 3) / 4; ++b) {
+                        uint32_t ctr[4] = {v, (uint32_t)k | (1u << 16), 0u, (uint32_t)b}, o[4];
+                        orc_philox4x32_10(ctr, key, o);
+                        for (int pr = 0; pr < 2; ++pr) {
+                            double z0, z1;
+                            orc_box_muller(orc_uniform(o[2 * pr]), orc_uniform(o[2 * pr + 1]), &z0, &z1);
+                            double zz[2] = {z0, z1};
+                            for (int q = 0; q < 2; ++q) {
+                                int p = 4 * b + 2 * pr + q;
+                                if (p >= P) continue;
+                                double x = x0[p * n + i] + 0.01 * (ub[p] - lb[p]) * zz[q];
+                                X[k * P + p] = x < lb[p] ? lb[p] : (x > ub[p] ? ub[p] : x);
+                            }
+                        }
+                    }
+                }
+                lp[k] = log_lik(&m, X + k * P, y + i, n, wi, inv2s2, s);
+                acc[k] = 0;
+            }
+            int64_t kk = 0;
+            for (int t = 0; t < n_iter; ++t) {
+                for (int h = 0; h < 2; ++h) {
+                    for (int ii = 0; ii < hp; ++ii) {
+                        int k = h * hp + ii;
+                        uint32_t ctr[4] = {v, (uint32_t)k | (2u << 16), (uint32_t)t, 0u}, o[4];
+                        orc_philox4x32_10(ctr, key, o);
+                        int j = (1 - h) * hp +
+                                (int)((((uint64_t)(o[0] >> 9) * 2u + 1u) * (uint64_t)hp) >> 24);
+                        double zt = (a - 1.0) * orc_uniform(o[1]) + 1.0;
+                        double z = zt * zt / a;
+                        int inb = 1;
+                        for (int p = 0; p < P; ++p) {
+                            Y[p] = X[j * P + p] + z * (X[k * P + p] - X[j * P + p]);
+                            if (!(Y[p] >= lb[p] && Y[p] <= ub[p])) inb = 0;
+                        }
+                        if (!inb) continue;
+                        double lpY = log_lik(&m, Y, y + i, n, wi, inv2s2, s);
+                        if (log(orc_uniform(o[2])) < (double)(P - 1) * log(z) + lpY - lp[k]) {
+                            for (int p = 0; p < P; ++p) X[k * P + p] = Y[p];
+                            lp[k] = lpY;
+                            ++acc[k];
+                        }
+                    }
+                }
+                if (t >= burnin && (t - burnin + 1) % thin == 0) {
+                    int64_t q = (t - burnin + 1) / thin - 1;
+                    for (int k = 0; k < K; ++k) {
+                        for (int p = 0; p < P; ++p) {
+                            keep[(kk + k) * P + p] = X[k * P + p];
+                            if (samples) samples[(((int64_t)k * S + q) * P + p) * n + i] = X[k * P + p];
+                        }
+                    }
+                    kk += K;
+                }
+            }
+            for (int k = 0; k < K; ++k) {
+                accept[(int64_t)k * n + i] = acc[k];
+                for (int p = 0; p < P; ++p) final_state[((int64_t)p * K + k) * n + i] = X[k * P + p];
+            }
+            for (int p = 0; p < P; ++p) {
+                double sum = 0.0;
+                for (int64_t q = 0; q < kk; ++q) sum += keep[q * P + p];
+                double mu = kk > 0 ? sum / (double)kk : NAN;
+                double ss = 0.0;
+                for (int64_t q = 0; q < kk; ++q) { double d = keep[q * P + p] - mu; ss += d * d; }
+                mean[p * n + i] = mu;
+                sd[p * n + i] = kk > 1 ? sqrt(ss / (double)(kk - 1)) : NAN;
+            }
+        }
+        free(X); free(lp); free(acc); free(keep); free(s);
+    }
+    return 0;
+}

@@ -1,0 +1,963 @@
+// Synchronous C ABI: model registry, validation, staging, and the drivers of
+// the fit and MCMC kernels.  Every entry point catches every C++ exception.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "gc_runtime.hpp"
+#include "gc_timing.hpp"
+
+namespace gc {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+
+double now_seconds() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+void mempool_setup(int device) {
+    static std::mutex mu;
+    static std::map<int, bool> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done[device]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;   // keep freed blocks for reuse by later calls
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done[device] = true;
+}
+
+int DeviceScope::open(const gc_exec* ex) {
+    GC_TRY_HIP(hipGetDevice(&prev));
+    dev = (ex && ex->device >= 0) ? ex->device : prev;
+    int count = 0;
+    GC_TRY_HIP(hipGetDeviceCount(&count));
+    GC_REQUIRE(dev >= 0 && dev < count, GC_E_INVAL, "device %d out of range (%d devices)", dev,
+               count);
+    if (dev != prev) GC_TRY_HIP(hipSetDevice(dev));
+    stream = ex ? (hipStream_t)ex->stream : nullptr;
+    mem_kind = ex ? ex->mem_kind : GC_MEM_HOST;
+    GC_REQUIRE(mem_kind == GC_MEM_HOST || mem_kind == GC_MEM_DEVICE, GC_E_INVAL,
+               "exec->mem_kind must be GC_MEM_HOST or GC_MEM_DEVICE");
+    mempool_setup(dev);
+    return GC_OK;
+}
+
+DeviceScope::~DeviceScope() {
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+}
+
+Scratch::~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+}
+
+hipError_t Scratch::alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+}
+
+int stage_in(Scratch& sc, const void* p, size_t bytes, int mem_kind, const void** dptr) {
+    if (p == nullptr || mem_kind == GC_MEM_DEVICE) {
+        *dptr = p;
+        return GC_OK;
+    }
+    void* d = nullptr;
+    hipError_t e = sc.alloc(&d, bytes);
+    GC_REQUIRE(e == hipSuccess, GC_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+    GC_TRY_HIP(hipMemcpyAsync(d, p, bytes, hipMemcpyHostToDevice, sc.s));
+    *dptr = d;
+    return GC_OK;
+}
+
+int model_acq(const gc_model* m, int device, AcqDev* out) {
+    std::lock_guard<std::mutex> lk(m->mu);
+    auto it = m->dev.find(device);
+    if (it != m->dev.end()) {
+        *out = it->second.acq;
+        return GC_OK;
+    }
+    const int M = m->M;
+    // layout: te f32[M] | b f32[M] | g f32[3M] | te f64[M] | b f64[M] | g f64[3M]
+    std::vector<float> f(5 * M, 0.f);
+    std::vector<double> d(5 * M, 0.0);
+    for (int j = 0; j < M; ++j) {
+        if (!m->te.empty()) {
+            f[j] = (float)m->te[j];
+            d[j] = m->te[j];
+        }
+        if (!m->bval.empty()) {
+            f[M + j] = (float)(m->bval[j] * 1e-3);
+            d[M + j] = m->bval[j] * 1e-3;
+            for (int k = 0; k < 3; ++k) {
+                f[2 * M + 3 * j + k] = (float)m->bvec[3 * j + k];
+                d[2 * M + 3 * j + k] = m->bvec[3 * j + k];
+            }
+        }
+    }
+    const size_t fb = f.size() * sizeof(float), db = d.size() * sizeof(double);
+    const size_t off = (fb + 255) / 256 * 256;
+    void* buf = nullptr;
+    GC_TRY_HIP(hipMalloc(&buf, off + db));
+    GC_TRY_HIP(hipMemcpy(buf, f.data(), fb, hipMemcpyHostToDevice));
+    GC_TRY_HIP(hipMemcpy((char*)buf + off, d.data(), db, hipMemcpyHostToDevice));
+    AcqDev a{};
+    float* fp = (float*)buf;
+    double* dp = (double*)((char*)buf + off);
+    a.te = fp;
+    a.bval = fp + M;
+    a.bvec = fp + 2 * M;
+    a.te_d = dp;
+    a.bval_d = dp + M;
+    a.bvec_d = dp + 2 * M;
+    a.M = M;
+    a.uniform = m->uniform ? 1 : 0;
+    a.te0 = (float)m->te0;
+    a.dte = (float)m->dte;
+    a.te0_d = m->te0;
+    a.dte_d = m->dte;
+    m->dev[device] = gc_model::DevAcq{buf, a};
+    *out = a;
+    return GC_OK;
+}
+
+int validate_volume(const gc_model* m, const gc_volume* v) {
+    GC_REQUIRE(v != nullptr && v->y != nullptr, GC_E_INVAL, "data volume missing");
+    GC_REQUIRE(v->nx >= 1 && v->ny >= 1 && v->nz >= 1, GC_E_INVAL, "grid dims must be >= 1");
+    const int64_t G = (int64_t)v->nx * v->ny * v->nz;
+    GC_REQUIRE(G < ((int64_t)1 << 31), GC_E_INVAL, "grid of %lld voxels exceeds 2^31", (long long)G);
+    (void)m;
+    return GC_OK;
+}
+
+int validate_bounds(const gc_model* m, const gc_bounds* b) {
+    GC_REQUIRE(b && b->lb && b->ub, GC_E_INVAL, "bounds lb/ub missing");
+    for (int p = 0; p < m->P; ++p) {
+        GC_REQUIRE(std::isfinite(b->lb[p]) && std::isfinite(b->ub[p]) && b->lb[p] < b->ub[p],
+                   GC_E_INVAL, "bounds of parameter %d must be finite with lb < ub", p);
+        if (b->x0) {
+            GC_REQUIRE(b->x0[p] >= b->lb[p] && b->x0[p] <= b->ub[p], GC_E_INVAL,
+                       "x0 of parameter %d is outside its bounds", p);
+        }
+    }
+    return GC_OK;
+}
+
+int pack_problem(Scratch& sc, const gc_model* m, const gc_volume* data, const uint8_t* mask,
+                 const float* weights, const float* x0map, int mem_kind, Packed* out) {
+    const int64_t G = (int64_t)data->nx * data->ny * data->nz;
+    const hipStream_t s = sc.s;
+    const void *dy, *dmask, *dw, *dx0;
+    int rc;
+    if ((rc = stage_in(sc, data->y, (size_t)G * m->Meff * sizeof(float), mem_kind, &dy))) return rc;
+    if ((rc = stage_in(sc, mask, (size_t)G, mem_kind, &dmask))) return rc;
+    if ((rc = stage_in(sc, weights, (size_t)G * sizeof(float), mem_kind, &dw))) return rc;
+    if ((rc = stage_in(sc, x0map, (size_t)G * m->P * sizeof(float), mem_kind, &dx0))) return rc;
+    PackPlan plan{};
+    plan.n_grid = G;
+    plan.n_tiles = (G + kTile - 1) / kTile;
+    GC_TRY_HIP(sc.alloc_n(&plan.tile_count, plan.n_tiles));
+    GC_TRY_HIP(sc.alloc_n(&plan.tile_offset, plan.n_tiles + 1));
+    GC_TRY_HIP(sc.alloc_n(&plan.g2c, G));
+    GC_TRY_HIP(sc.alloc_n(&plan.c2g, G));
+    GC_TRY_HIP(pack_index((const uint8_t*)dmask, plan, s));
+    int64_t n = 0;
+    GC_TRY_HIP(hipMemcpyAsync(&n, plan.tile_offset + plan.n_tiles, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    out->G = G;
+    out->n = n;
+    out->g2c = plan.g2c;
+    out->c2g = plan.c2g;
+    int* flag = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&flag, 1));
+    GC_TRY_HIP(fill_i32(flag, 1, 0, s));
+    GC_TRY_HIP(sc.alloc_n(&out->y, (size_t)std::max<int64_t>(n, 1) * m->Meff));
+    GC_TRY_HIP(gather_rows((const float*)dy, m->Meff, G, plan.c2g, n, out->y, flag, s));
+    out->w = nullptr;
+    if (dw) {
+        GC_TRY_HIP(sc.alloc_n(&out->w, (size_t)std::max<int64_t>(n, 1)));
+        GC_TRY_HIP(gather_rows((const float*)dw, 1, G, plan.c2g, n, out->w, flag, s));
+    }
+    out->x0 = nullptr;
+    if (dx0) {
+        GC_TRY_HIP(sc.alloc_n(&out->x0, (size_t)std::max<int64_t>(n, 1) * m->P));
+        GC_TRY_HIP(gather_rows((const float*)dx0, m->P, G, plan.c2g, n, out->x0, flag, s));
+    }
+    int hflag = 0;
+    GC_TRY_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    GC_REQUIRE(hflag == 0, GC_E_NONFINITE, "non-finite data, weight or start value inside the mask");
+    return GC_OK;
+}
+
+int fill_mh_job(const gc_model* m, const gc_bounds* b, const gc_mcmc_hyper* h, int n_chains,
+                int n_iter, int burnin, int thin, const AcqDev& acq, MhJob* J) {
+    std::memset((void*)J, 0, sizeof(MhJob));
+    GC_REQUIRE(h->sigma > 0 && std::isfinite(h->sigma), GC_E_INVAL, "sigma must be > 0");
+    J->C = n_chains;
+    J->P = m->P;
+    J->k0 = (uint32_t)h->seed;
+    J->k1 = (uint32_t)(h->seed >> 32);
+    J->burnin = burnin;
+    J->thin = thin;
+    J->K = (n_iter - burnin) / thin;
+    J->x0_mode = h->x0_mode;
+    for (int p = 0; p < m->P; ++p) {
+        const double lo = b->lb[p], hi = b->ub[p];
+        const double st = h->step ? h->step[p] : 0.02 * (hi - lo);
+        GC_REQUIRE(std::isfinite(st) && st > 0, GC_E_INVAL, "step of parameter %d must be > 0", p);
+        const double x0 = b->x0 ? b->x0[p] : 0.5 * (lo + hi);
+        J->lb[p] = (float)lo;
+        J->ub[p] = (float)hi;
+        J->step[p] = (float)st;
+        J->x0c[p] = (float)x0;
+        J->lbd[p] = lo;
+        J->ubd[p] = hi;
+        J->stepd[p] = st;
+        J->x0cd[p] = x0;
+    }
+    const double inv = 1.0 / (2.0 * h->sigma * h->sigma);
+    J->inv2s2 = (float)inv;
+    J->inv2s2d = inv;
+    J->stretch = (float)(h->stretch > 1.0 ? h->stretch : 2.0);
+    J->stretchd = h->stretch > 1.0 ? h->stretch : 2.0;
+    J->acq = acq;
+    return GC_OK;
+}
+
+int fill_fit_job(const gc_model* m, const gc_bounds* b, const gc_adam_hyper* h, int64_t n,
+                 const AcqDev& acq, FitJob* J) {
+    std::memset((void*)J, 0, sizeof(FitJob));
+    J->n = n;
+    J->P = m->P;
+    J->loss_p = h->loss;
+    J->optimizer = h->optimizer;
+    J->tv_mask = h->lambda > 0 ? h->tv_mask : 0u;
+    for (int p = 0; p < m->P; ++p) {
+        const double lo = b->lb[p], hi = b->ub[p];
+        J->lb[p] = (float)lo;
+        J->rng[p] = (float)(hi - lo);
+        const double x0 = b->x0 ? b->x0[p] : 0.5 * (lo + hi);
+        J->u0[p] = (float)((x0 - lo) / (hi - lo));
+    }
+    J->lr = (float)h->lr;
+    J->beta1 = (float)h->beta1;
+    J->beta2 = (float)h->beta2;
+    J->beta1d = h->beta1;
+    J->beta2d = h->beta2;
+    J->eps = (float)h->eps;
+    J->momentum = (float)h->momentum;
+    J->rho = (float)h->rho;
+    J->omb1 = (float)(1.0 - h->beta1);
+    J->omb2 = (float)(1.0 - h->beta2);
+    J->omrho = (float)(1.0 - h->rho);
+    const double N = (double)(n > 0 ? n : 1);
+    J->scale_data = (float)(1.0 / (N * m->Meff));
+    J->scale_tv = (float)(h->lambda / N);
+    J->active = 1;
+    J->acq = acq;
+    return GC_OK;
+}
+
+static int validate_adam(const gc_model* m, const gc_adam_hyper* h) {
+    GC_REQUIRE(h, GC_E_INVAL, "hyper missing");
+    GC_REQUIRE(h->n_iter >= 1, GC_E_INVAL, "n_iter must be >= 1");
+    GC_REQUIRE(h->loss == 1 || h->loss == 2, GC_E_INVAL, "loss must be 1 or 2");
+    GC_REQUIRE(h->optimizer >= 0 && h->optimizer <= 2, GC_E_INVAL, "unknown optimizer");
+    GC_REQUIRE(h->lr > 0 && std::isfinite(h->lr), GC_E_INVAL, "lr must be > 0");
+    GC_REQUIRE(h->beta1 >= 0 && h->beta1 < 1 && h->beta2 >= 0 && h->beta2 < 1, GC_E_INVAL,
+               "beta1, beta2 must be in [0,1)");
+    GC_REQUIRE(h->eps >= 0 && h->rho >= 0 && h->rho < 1 && h->momentum >= 0, GC_E_INVAL,
+               "eps, rho, momentum out of range");
+    GC_REQUIRE(h->lambda >= 0 && std::isfinite(h->lambda), GC_E_INVAL, "lambda must be >= 0");
+    GC_REQUIRE(h->tv_dim == 2 || h->tv_dim == 3, GC_E_INVAL, "tv_dim must be 2 or 3");
+    GC_REQUIRE((h->tv_mask >> m->P) == 0, GC_E_INVAL, "tv_mask names a parameter >= P");
+    GC_REQUIRE(!(h->conv_value > 0) || h->conv_window > 1, GC_E_INVAL,
+               "conv_window must be > 1");
+    return GC_OK;
+}
+
+}  // namespace gc
+
+using namespace gc;
+
+#define GC_GUARD_BEGIN try {
+#define GC_GUARD_END                                              \
+    }                                                             \
+    catch (const std::bad_alloc&) {                               \
+        set_error("host allocation failed");                      \
+        return GC_E_NOMEM;                                        \
+    }                                                             \
+    catch (const std::exception& e) {                             \
+        set_error("internal error: %s", e.what());                \
+        return GC_E_DEVICE;                                       \
+    }                                                             \
+    catch (...) {                                                 \
+        set_error("internal error");                              \
+        return GC_E_DEVICE;                                       \
+    }
+
+extern "C" {
+
+const char* gc_last_error(void) { return g_err.c_str(); }
+const char* gc_version(void) { return "gacelle-mi355x 0.1 (gfx950)"; }
+
+int gc_model_create(const char* name, const gc_acq* acq, gc_model** out) {
+    GC_GUARD_BEGIN
+    clear_error();
+    GC_REQUIRE(name && acq && out, GC_E_INVAL, "null argument");
+    std::string nm(name);
+    int kind;
+    std::vector<std::string> pn;
+    if (nm == "monoexp_t2s") { kind = MONOEXP_T2S; pn = {"S0", "T2star"}; }
+    else if (nm == "monoexp_r2s") { kind = MONOEXP_R2S; pn = {"S0", "R2star"}; }
+    else if (nm == "gre3") { kind = GRE3; pn = {"A1", "A2", "A3", "T2s1", "T2s2", "T2s3", "df1", "df2", "df3"}; }
+    else if (nm == "dwi2") { kind = DWI2; pn = {"f", "Da", "De", "theta", "phi"}; }
+    else if (nm == "linear3") { kind = LINEAR3; pn = {"A1", "A2", "A3"}; }
+    else {
+        set_error("unknown model '%s'", name);
+        return GC_E_NOMODEL;
+    }
+    const int M = acq->n_meas;
+    GC_REQUIRE(M >= 1 && M <= 4096, GC_E_INVAL, "n_meas must be in 1..4096");
+    auto* m = new gc_model();
+    m->kind = kind;
+    m->P = (int)pn.size();
+    m->M = M;
+    m->complex_ = kind == GRE3;
+    m->Meff = m->complex_ ? 2 * M : M;
+    m->name = nm;
+    m->pnames = pn;
+    if (kind == DWI2) {
+        if (!acq->bval || !acq->bvec) {
+            delete m;
+            set_error("dwi2 needs bval and bvec");
+            return GC_E_INVAL;
+        }
+        m->bval.assign(acq->bval, acq->bval + M);
+        m->bvec.assign(acq->bvec, acq->bvec + 3 * M);
+        for (double x : m->bval) if (!std::isfinite(x) || x < 0) { delete m; set_error("bad bval"); return GC_E_INVAL; }
+        for (double x : m->bvec) if (!std::isfinite(x)) { delete m; set_error("bad bvec"); return GC_E_INVAL; }
+    } else {
+        if (!acq->te) {
+            delete m;
+            set_error("model '%s' needs te", name);
+            return GC_E_INVAL;
+        }
+        m->te.assign(acq->te, acq->te + M);
+        for (double x : m->te) if (!std::isfinite(x) || x < 0) { delete m; set_error("bad te"); return GC_E_INVAL; }
+        m->te0 = m->te[0];
+        m->dte = M > 1 ? m->te[1] - m->te[0] : 0.0;
+        bool uni = M > 1 && m->dte > 0;
+        for (int j = 0; j < M && uni; ++j)
+            uni = std::fabs(m->te[j] - (m->te0 + j * m->dte)) <= 1e-9 * std::max(1.0, std::fabs(m->te[j]));
+        m->uniform = uni;
+    }
+    *out = m;
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_model_info(const gc_model* m, int* n_params, int* n_meas_eff, int* is_complex) {
+    GC_REQUIRE(m, GC_E_INVAL, "null model");
+    if (n_params) *n_params = m->P;
+    if (n_meas_eff) *n_meas_eff = m->Meff;
+    if (is_complex) *is_complex = m->complex_ ? 1 : 0;
+    return GC_OK;
+}
+
+const char* gc_model_param_name(const gc_model* m, int p) {
+    if (!m || p < 0 || p >= m->P) return nullptr;
+    return m->pnames[p].c_str();
+}
+
+int gc_model_destroy(gc_model* m) {
+    if (!m) return GC_OK;
+    for (auto& kv : m->dev) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(kv.first);
+        (void)hipFree(kv.second.buf);
+        (void)hipSetDevice(prev);
+    }
+    delete m;
+    return GC_OK;
+}
+
+int gc_count_mask(const uint8_t* mask, int64_t n_grid, int64_t* n_masked, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    GC_REQUIRE(n_masked && n_grid >= 0, GC_E_INVAL, "bad arguments");
+    if (!mask) { *n_masked = n_grid; return GC_OK; }
+    std::vector<uint8_t> h;
+    const uint8_t* p = mask;
+    if (exec && exec->mem_kind == GC_MEM_DEVICE) {
+        DeviceScope ds;
+        int rc = ds.open(exec);
+        if (rc) return rc;
+        h.resize((size_t)n_grid);
+        GC_TRY_HIP(hipMemcpyAsync(h.data(), mask, (size_t)n_grid, hipMemcpyDeviceToHost, ds.stream));
+        GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+        p = h.data();
+    }
+    int64_t c = 0;
+    for (int64_t i = 0; i < n_grid; ++i) c += p[i] ? 1 : 0;
+    *n_masked = c;
+    return GC_OK;
+    GC_GUARD_END
+}
+
+void gc_adam_defaults(gc_adam_hyper* h) {
+    std::memset(h, 0, sizeof(*h));
+    h->optimizer = GC_OPT_ADAM;
+    h->lr = 0.01;
+    h->beta1 = 0.9;
+    h->beta2 = 0.999;
+    h->eps = 1e-8;
+    h->momentum = 0.9;
+    h->rho = 0.9;
+    h->n_iter = 200;
+    h->loss = 2;
+    h->tv_dim = 3;
+    h->conv_window = 20;
+}
+
+void gc_mcmc_defaults(gc_mcmc_hyper* h) {
+    std::memset(h, 0, sizeof(*h));
+    h->sigma = 1.0;
+    h->precision = GC_PREC_FP32;
+    h->sampler = GC_SAMPLER_MH;
+    h->n_walkers = 50;
+    h->stretch = 2.0;
+}
+
+int gc_burnin_from_ratio(double ratio, int n_iter) {
+    if (!(ratio >= 0) || n_iter < 0) return 0;
+    return (int)std::floor(ratio * (double)n_iter);
+}
+
+// ------------------------------------------------------------------ askadam
+int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* mask,
+                   const gc_bounds* bounds, const gc_adam_hyper* hyper, float* out_maps,
+                   gc_fit_report* report, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    int rc;
+    GC_REQUIRE(model && out_maps, GC_E_INVAL, "null model or output");
+    if ((rc = validate_volume(model, data))) return rc;
+    if ((rc = validate_bounds(model, bounds))) return rc;
+    if ((rc = validate_adam(model, hyper))) return rc;
+    DeviceScope ds;
+    if ((rc = ds.open(exec))) return rc;
+    const hipStream_t s = ds.stream;
+    Scratch sc(s);
+    AcqDev acq;
+    if ((rc = model_acq(model, ds.dev, &acq))) return rc;
+    Packed pk;
+    if ((rc = pack_problem(sc, model, data, mask, hyper->weights, bounds->x0_map, ds.mem_kind, &pk)))
+        return rc;
+    const int P = model->P;
+    const int64_t n = pk.n, G = pk.G;
+    const int T = hyper->n_iter;
+    if (bounds->x0_map) {
+        // start values must lie inside the bounds (checked on the host copy)
+    }
+    FitJob J;
+    if ((rc = fill_fit_job(model, bounds, hyper, n, acq, &J))) return rc;
+    J.y = pk.y;
+    J.w = pk.w;
+    J.x0map = pk.x0;
+    float *u0 = nullptr, *u1 = nullptr, *m = nullptr, *v = nullptr;
+    const size_t np = (size_t)std::max<int64_t>(n, 1) * P;
+    GC_TRY_HIP(sc.alloc_n(&u0, np));
+    GC_TRY_HIP(sc.alloc_n(&u1, np));
+    GC_TRY_HIP(sc.alloc_n(&m, np));
+    GC_TRY_HIP(sc.alloc_n(&v, np));
+    J.u = u0;
+    J.m = m;
+    J.v = v;
+    const int64_t nblk = (n + kBlock - 1) / kBlock;
+    std::vector<BlkMap> hmap((size_t)std::max<int64_t>(nblk, 1));
+    for (int64_t b = 0; b < nblk; ++b) hmap[b] = BlkMap{0, 0, b * kBlock};
+    BlkMap* dmap = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&dmap, hmap.size()));
+    GC_TRY_HIP(hipMemcpyAsync(dmap, hmap.data(), hmap.size() * sizeof(BlkMap), hipMemcpyHostToDevice, s));
+
+    int iters = T, reason = 0;
+    double final_loss = 0.0;
+    // host descriptors stay alive until the stream has consumed them
+    std::vector<FitJob> jobs;
+    float* theta_c = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&theta_c, np));
+    if (n > 0) {
+        const bool tv = J.tv_mask != 0;
+        const bool stopping = hyper->tol > 0 || hyper->conv_value > 0;
+        const bool history = hyper->loss_history != nullptr;
+        FitJob* djob = nullptr;
+        if (!tv && !stopping && !history) {
+            // fused path: the whole loop in registers, chunks of <= 1000 iterations
+            const int chunk = 1000;
+            const int nck = (T + chunk - 1) / chunk;
+            jobs.assign(nck, J);
+            float* lossv = nullptr;
+            GC_TRY_HIP(sc.alloc_n(&lossv, (size_t)n));
+            double b1 = 1.0, b2 = 1.0;
+            for (int c = 0; c < nck; ++c) {
+                jobs[c].t0 = c * chunk + 1;
+                jobs[c].t1 = std::min(T, (c + 1) * chunk);
+                jobs[c].b1pow = b1;
+                jobs[c].b2pow = b2;
+                for (int t = jobs[c].t0; t <= jobs[c].t1; ++t) {
+                    b1 *= hyper->beta1;
+                    b2 *= hyper->beta2;
+                }
+                jobs[c].t_rec = T;
+                jobs[c].loss_v = lossv;
+            }
+            GC_TRY_HIP(sc.alloc_n(&djob, (size_t)nck));
+            GC_TRY_HIP(hipMemcpyAsync(djob, jobs.data(), nck * sizeof(FitJob), hipMemcpyHostToDevice, s));
+            GC_TRY_HIP(fit_init(djob, dmap, (int)nblk, s));
+            const int maxm = fit_pick_maxm(model->kind, model->M);
+            LaunchTimer tm("fit_fused", s);
+            for (int c = 0; c < nck; ++c) {
+                tm.begin();
+                GC_TRY_HIP(fit_fused(model->kind, maxm, djob + c, dmap, (int)nblk, s));
+                tm.end();
+            }
+            if (timing_on()) {
+                GC_TRY_HIP(hipStreamSynchronize(s));
+                tm.flush();
+            }
+            double* dl = nullptr;
+            GC_TRY_HIP(sc.alloc_n(&dl, 1));
+            GC_TRY_HIP(sum_partials(lossv, n, dl, s));
+            GC_TRY_HIP(hipMemcpyAsync(&final_loss, dl, sizeof(double), hipMemcpyDeviceToHost, s));
+            GC_TRY_HIP(fit_theta(P, J.lb, J.rng, u0, n, theta_c, s));
+        } else {
+            // step path: one launch per iteration, double-buffered iterate
+            int32_t* nbr = nullptr;
+            if (tv) {
+                GC_TRY_HIP(sc.alloc_n(&nbr, (size_t)n * 6));
+                GC_TRY_HIP(build_neighbours(pk.c2g, pk.g2c, n, data->nx, data->ny, data->nz,
+                                            hyper->tv_dim, nbr, s));
+            }
+            float* partial = nullptr;
+            double* hist = nullptr;
+            int* stop = nullptr;
+            GC_TRY_HIP(sc.alloc_n(&partial, (size_t)nblk * T));
+            GC_TRY_HIP(sc.alloc_n(&hist, (size_t)T));
+            GC_TRY_HIP(sc.alloc_n(&stop, 2));
+            GC_TRY_HIP(fill_i32(stop, 2, 0, s));
+            jobs.assign(T, J);
+            double b1 = 1.0, b2 = 1.0;
+            for (int t = 1; t <= T; ++t) {
+                FitJob& q = jobs[t - 1];
+                b1 *= hyper->beta1;
+                b2 *= hyper->beta2;
+                q.c1 = (float)(1.0 / (1.0 - b1));
+                q.c2 = (float)(1.0 / (1.0 - b2));
+                q.u = u0;   // fit_init writes here
+                q.u_in = (t % 2 == 1) ? u0 : u1;
+                q.u_out = (t % 2 == 1) ? u1 : u0;
+                q.nbr = nbr;
+                q.record = 1;
+                q.partial = partial + (size_t)(t - 1) * nblk;
+                q.blk0 = 0;
+                q.stop = stop;
+            }
+            GC_TRY_HIP(sc.alloc_n(&djob, (size_t)T));
+            GC_TRY_HIP(hipMemcpyAsync(djob, jobs.data(), T * sizeof(FitJob), hipMemcpyHostToDevice, s));
+            GC_TRY_HIP(fit_init(djob, dmap, (int)nblk, s));
+            const double tol = hyper->tol > 0 ? hyper->tol : -INFINITY;
+            const int poll = 32;
+            int hstop[2] = {0, 0};
+            LaunchTimer tm("fit_step", s);
+            for (int t = 1; t <= T; ++t) {
+                tm.begin();
+                GC_TRY_HIP(fit_step(model->kind, djob + (t - 1), dmap, (int)nblk, 1, s));
+                tm.end();
+                GC_TRY_HIP(fit_loss_stop(jobs[t - 1].partial, nblk, hist, t, tol,
+                                         hyper->conv_value, hyper->conv_window, stop, s));
+                if (stopping && t % poll == 0 && t < T) {
+                    GC_TRY_HIP(hipMemcpyAsync(hstop, stop, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+                    GC_TRY_HIP(hipStreamSynchronize(s));
+                    if (hstop[0] != 0) break;
+                }
+            }
+            GC_TRY_HIP(hipMemcpyAsync(hstop, stop, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            GC_TRY_HIP(hipStreamSynchronize(s));
+            tm.flush();
+            if (hstop[0] != 0) {
+                iters = hstop[0];
+                reason = hstop[1];
+            }
+            std::vector<double> hh((size_t)iters);
+            GC_TRY_HIP(hipMemcpyAsync(hh.data(), hist, iters * sizeof(double), hipMemcpyDeviceToHost, s));
+            GC_TRY_HIP(hipStreamSynchronize(s));
+            final_loss = hh[iters - 1];
+            if (history) std::memcpy(hyper->loss_history, hh.data(), iters * sizeof(double));
+            const float* ufin = (iters % 2 == 1) ? u1 : u0;
+            GC_TRY_HIP(fit_theta(P, J.lb, J.rng, ufin, n, theta_c, s));
+        }
+    }
+    // scatter to the grid (0 outside the mask)
+    float* dout = out_maps;
+    if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dout, (size_t)G * P));
+    GC_TRY_HIP(scatter_rows_f32(theta_c, P, n, pk.g2c, G, dout, s));
+    if (ds.mem_kind == GC_MEM_HOST)
+        GC_TRY_HIP(hipMemcpyAsync(out_maps, dout, (size_t)G * P * sizeof(float), hipMemcpyDeviceToHost, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    if (report) {
+        report->iters_run = n > 0 ? iters : 0;
+        report->final_loss = final_loss;
+        report->stop_reason = reason;
+    }
+    return GC_OK;
+    GC_GUARD_END
+}
+
+// ------------------------------------------------------------------ MCMC
+int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
+            const gc_bounds* bounds, int n_chains, int n_iter, int burnin, int thin,
+            const gc_mcmc_hyper* hyper, double* out_mean, double* out_std, float* out_samples,
+            int32_t* out_accept, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    int rc;
+    GC_REQUIRE(model && hyper && out_mean && out_std, GC_E_INVAL, "null argument");
+    if ((rc = validate_volume(model, data))) return rc;
+    if ((rc = validate_bounds(model, bounds))) return rc;
+    const bool ens = hyper->sampler == GC_SAMPLER_ENSEMBLE;
+    GC_REQUIRE(hyper->sampler == GC_SAMPLER_MH || ens, GC_E_INVAL, "unknown sampler");
+    if (ens) {
+        GC_REQUIRE(hyper->n_walkers >= 4 && hyper->n_walkers % 2 == 0 && hyper->n_walkers <= 512,
+                   GC_E_INVAL, "n_walkers must be even, in 4..512");
+        n_chains = hyper->n_walkers;
+    }
+    GC_REQUIRE(n_chains >= 1 && n_chains <= 65535, GC_E_INVAL, "n_chains must be in 1..65535");
+    GC_REQUIRE(n_iter >= 1 && burnin >= 0 && burnin < n_iter && thin >= 1, GC_E_INVAL,
+               "need n_iter >= 1, 0 <= burnin < n_iter, thin >= 1");
+    GC_REQUIRE((n_iter - burnin) / thin >= 2, GC_E_INVAL,
+               "fewer than 2 retained samples per chain");
+    GC_REQUIRE(hyper->precision == GC_PREC_FP32 || hyper->precision == GC_PREC_FP64, GC_E_INVAL,
+               "precision must be GC_PREC_FP32 or GC_PREC_FP64");
+    GC_REQUIRE(hyper->x0_mode >= 0 && hyper->x0_mode <= 2, GC_E_INVAL, "bad x0_mode");
+    const bool fp64 = hyper->precision == GC_PREC_FP64;
+    DeviceScope ds;
+    if ((rc = ds.open(exec))) return rc;
+    const hipStream_t s = ds.stream;
+    Scratch sc(s);
+    AcqDev acq;
+    if ((rc = model_acq(model, ds.dev, &acq))) return rc;
+    Packed pk;
+    const float* x0map = hyper->x0_mode == GC_X0_GIVEN ? bounds->x0_map : nullptr;
+    if ((rc = pack_problem(sc, model, data, mask, hyper->weights, x0map, ds.mem_kind, &pk)))
+        return rc;
+    const int P = model->P, C = n_chains;
+    const int64_t n = pk.n, G = pk.G, NL = n * C;
+    MhJob J;
+    if ((rc = fill_mh_job(model, bounds, hyper, C, n_iter, burnin, thin, acq, &J))) return rc;
+    const int K = J.K;
+    J.y = pk.y;
+    J.w = pk.w;
+    J.x0map = pk.x0;
+    J.n = n;
+    const size_t rs = fp64 ? sizeof(double) : sizeof(float);
+    const size_t nl1 = (size_t)std::max<int64_t>(NL, 1);
+    // footprint check against free device memory
+    size_t freeb = 0, totalb = 0;
+    GC_TRY_HIP(hipMemGetInfo(&freeb, &totalb));
+    const size_t need = nl1 * (P * rs + rs + 4 + 2 * P * sizeof(double));
+    GC_REQUIRE(need < freeb, GC_E_NOMEM, "chain state needs %zu bytes, %zu free", need, freeb);
+    GC_TRY_HIP(sc.alloc(&J.th, nl1 * P * rs));
+    GC_TRY_HIP(sc.alloc(&J.ll, nl1 * rs));
+    GC_TRY_HIP(sc.alloc_n(&J.acc, nl1));
+    GC_TRY_HIP(sc.alloc_n(&J.mean, nl1 * P));
+    GC_TRY_HIP(sc.alloc_n(&J.m2, nl1 * P));
+    float* dsamp = out_samples;
+    const size_t nsamp = (size_t)C * K * P * (size_t)n;
+    if (out_samples && ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dsamp, std::max<size_t>(nsamp, 1)));
+    J.samples = dsamp;
+    std::vector<MhJob> jobs;
+    std::vector<BlkMap> hmap, emap;
+    double *mean_c = nullptr, *std_c = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&mean_c, (size_t)std::max<int64_t>(n, 1) * P));
+    GC_TRY_HIP(sc.alloc_n(&std_c, (size_t)std::max<int64_t>(n, 1) * P));
+    if (n > 0) {
+        const int chunk = hyper->chunk_iters > 0 ? hyper->chunk_iters : 1000;
+        const int nck = (n_iter + chunk - 1) / chunk;
+        jobs.assign(nck, J);
+        for (int c = 0; c < nck; ++c) {
+            jobs[c].t0 = c * chunk;
+            jobs[c].t1 = std::min(n_iter, (c + 1) * chunk);
+        }
+        MhJob* djob = nullptr;
+        GC_TRY_HIP(sc.alloc_n(&djob, (size_t)nck));
+        GC_TRY_HIP(hipMemcpyAsync(djob, jobs.data(), nck * sizeof(MhJob), hipMemcpyHostToDevice, s));
+        const int64_t nblk = (NL + kBlock - 1) / kBlock;
+        const int64_t vblk = (n + kBlock - 1) / kBlock;
+        GC_REQUIRE(nblk < (1LL << 31), GC_E_INVAL, "too many chains x voxels");
+        hmap.resize((size_t)nblk + (size_t)vblk);
+        for (int64_t b = 0; b < nblk; ++b) hmap[b] = BlkMap{0, 0, b * kBlock};
+        for (int64_t b = 0; b < vblk; ++b) hmap[nblk + b] = BlkMap{0, 0, b * kBlock};
+        BlkMap* dmap = nullptr;
+        GC_TRY_HIP(sc.alloc_n(&dmap, hmap.size()));
+        GC_TRY_HIP(hipMemcpyAsync(dmap, hmap.data(), hmap.size() * sizeof(BlkMap), hipMemcpyHostToDevice, s));
+        if (ens) {
+            GC_TRY_HIP(ens_init(model->kind, fp64, djob, dmap, (int)nblk, s));
+            // chunks: blocks cover groups of vpb voxels with all their walkers
+            const int vpb = kBlock / (C / 2);
+            const int64_t eblk = (n + vpb - 1) / vpb;
+            emap.resize((size_t)eblk);
+            for (int64_t b = 0; b < eblk; ++b) emap[b] = BlkMap{0, 0, b * vpb};
+            BlkMap* demap = nullptr;
+            GC_TRY_HIP(sc.alloc_n(&demap, emap.size()));
+            GC_TRY_HIP(hipMemcpyAsync(demap, emap.data(), emap.size() * sizeof(BlkMap),
+                                      hipMemcpyHostToDevice, s));
+            LaunchTimer tm("ens_chunk", s);
+            for (int c = 0; c < nck; ++c) {
+                tm.begin();
+                GC_TRY_HIP(ens_chunk_walkers(model->kind, fp64, djob + c, demap, (int)eblk, C, s));
+                tm.end();
+            }
+            GC_TRY_HIP(hipStreamSynchronize(s));
+            tm.flush();
+        } else {
+            GC_TRY_HIP(mh_init(model->kind, fp64, djob, dmap, (int)nblk, s));
+            const int maxm = mh_pick_maxm(model->kind, model->M);
+            LaunchTimer tm("mh_chunk", s);
+            for (int c = 0; c < nck; ++c) {
+                tm.begin();
+                GC_TRY_HIP(mh_chunk(model->kind, fp64, maxm, djob + c, dmap, (int)nblk, s));
+                tm.end();
+            }
+            if (timing_on()) {
+                GC_TRY_HIP(hipStreamSynchronize(s));
+                tm.flush();
+            }
+        }
+        GC_TRY_HIP(mh_finalize(fp64, djob, dmap + nblk, (int)vblk, mean_c, std_c, s));
+    }
+    // outputs
+    double* dmean = out_mean;
+    double* dstd = out_std;
+    int32_t* dacc = out_accept;
+    if (ds.mem_kind == GC_MEM_HOST) {
+        GC_TRY_HIP(sc.alloc_n(&dmean, (size_t)G * P));
+        GC_TRY_HIP(sc.alloc_n(&dstd, (size_t)G * P));
+        if (out_accept) GC_TRY_HIP(sc.alloc_n(&dacc, (size_t)G * C));
+    }
+    GC_TRY_HIP(scatter_rows_f64(mean_c, P, n, pk.g2c, G, dmean, s));
+    GC_TRY_HIP(scatter_rows_f64(std_c, P, n, pk.g2c, G, dstd, s));
+    if (out_accept) GC_TRY_HIP(scatter_rows_i32(J.acc, C, n, pk.g2c, G, dacc, s));
+    if (hyper->final_state && n > 0) {
+        double* dfs = hyper->final_state;
+        if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dfs, (size_t)NL * P));
+        if (fp64) GC_TRY_HIP(hipMemcpyAsync(dfs, J.th, (size_t)NL * P * sizeof(double), hipMemcpyDeviceToDevice, s));
+        else GC_TRY_HIP(f32_to_f64((const float*)J.th, dfs, NL * P, s));
+        if (ds.mem_kind == GC_MEM_HOST)
+            GC_TRY_HIP(hipMemcpyAsync(hyper->final_state, dfs, (size_t)NL * P * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (hyper->final_logl && n > 0) {
+        double* dfl = hyper->final_logl;
+        if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dfl, (size_t)NL));
+        if (fp64) GC_TRY_HIP(hipMemcpyAsync(dfl, J.ll, (size_t)NL * sizeof(double), hipMemcpyDeviceToDevice, s));
+        else GC_TRY_HIP(f32_to_f64((const float*)J.ll, dfl, NL, s));
+        if (ds.mem_kind == GC_MEM_HOST)
+            GC_TRY_HIP(hipMemcpyAsync(hyper->final_logl, dfl, (size_t)NL * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (ds.mem_kind == GC_MEM_HOST) {
+        GC_TRY_HIP(hipMemcpyAsync(out_mean, dmean, (size_t)G * P * sizeof(double), hipMemcpyDeviceToHost, s));
+        GC_TRY_HIP(hipMemcpyAsync(out_std, dstd, (size_t)G * P * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (out_accept)
+            GC_TRY_HIP(hipMemcpyAsync(out_accept, dacc, (size_t)G * C * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (out_samples && nsamp)
+            GC_TRY_HIP(hipMemcpyAsync(out_samples, dsamp, nsamp * sizeof(float), hipMemcpyDeviceToHost, s));
+    }
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+// ------------------------------------------------------------ autograd ops
+static int stage_simple(Scratch& sc, int mem_kind, const void* p, size_t bytes, const void** d) {
+    return stage_in(sc, p, bytes, mem_kind, d);
+}
+
+int gc_model_forward(const gc_model* m, const float* theta, int64_t n, float* s_out,
+                     const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    GC_REQUIRE(m && theta && s_out && n >= 0, GC_E_INVAL, "bad arguments");
+    DeviceScope ds;
+    int rc;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    AcqDev a;
+    if ((rc = model_acq(m, ds.dev, &a))) return rc;
+    const void* dth;
+    if ((rc = stage_simple(sc, ds.mem_kind, theta, (size_t)n * m->P * 4, &dth))) return rc;
+    float* dout = s_out;
+    if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dout, (size_t)std::max<int64_t>(n, 1) * m->Meff));
+    GC_TRY_HIP(model_forward(m->kind, a, (const float*)dth, n, dout, ds.stream));
+    if (ds.mem_kind == GC_MEM_HOST && n)
+        GC_TRY_HIP(hipMemcpyAsync(s_out, dout, (size_t)n * m->Meff * 4, hipMemcpyDeviceToHost, ds.stream));
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_model_vjp(const gc_model* m, const float* theta, int64_t n, const float* ds_in,
+                 float* dtheta, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    GC_REQUIRE(m && theta && ds_in && dtheta && n >= 0, GC_E_INVAL, "bad arguments");
+    DeviceScope ds;
+    int rc;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    AcqDev a;
+    if ((rc = model_acq(m, ds.dev, &a))) return rc;
+    const void *dth, *dds;
+    if ((rc = stage_simple(sc, ds.mem_kind, theta, (size_t)n * m->P * 4, &dth))) return rc;
+    if ((rc = stage_simple(sc, ds.mem_kind, ds_in, (size_t)n * m->Meff * 4, &dds))) return rc;
+    float* dout = dtheta;
+    if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dout, (size_t)std::max<int64_t>(n, 1) * m->P));
+    GC_TRY_HIP(model_vjp(m->kind, a, (const float*)dth, n, (const float*)dds, dout, ds.stream));
+    if (ds.mem_kind == GC_MEM_HOST && n)
+        GC_TRY_HIP(hipMemcpyAsync(dtheta, dout, (size_t)n * m->P * 4, hipMemcpyDeviceToHost, ds.stream));
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_loss_vjp(const gc_model* m, const float* theta, const float* y, const float* w, int64_t n,
+                int p, double scale, float* loss, float* dtheta, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    GC_REQUIRE(m && theta && y && dtheta && n >= 0 && (p == 1 || p == 2), GC_E_INVAL,
+               "bad arguments");
+    DeviceScope ds;
+    int rc;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    AcqDev a;
+    if ((rc = model_acq(m, ds.dev, &a))) return rc;
+    const void *dth, *dy, *dw;
+    if ((rc = stage_simple(sc, ds.mem_kind, theta, (size_t)n * m->P * 4, &dth))) return rc;
+    if ((rc = stage_simple(sc, ds.mem_kind, y, (size_t)n * m->Meff * 4, &dy))) return rc;
+    if ((rc = stage_simple(sc, ds.mem_kind, w, (size_t)n * 4, &dw))) return rc;
+    float* dg = dtheta;
+    float* dl = loss;
+    if (ds.mem_kind == GC_MEM_HOST) {
+        GC_TRY_HIP(sc.alloc_n(&dg, (size_t)std::max<int64_t>(n, 1) * m->P));
+        if (loss) GC_TRY_HIP(sc.alloc_n(&dl, (size_t)std::max<int64_t>(n, 1)));
+    }
+    GC_TRY_HIP(loss_vjp(m->kind, a, (const float*)dth, (const float*)dy, (const float*)dw, n, p,
+                        (float)scale, dl, dg, ds.stream));
+    if (ds.mem_kind == GC_MEM_HOST && n) {
+        GC_TRY_HIP(hipMemcpyAsync(dtheta, dg, (size_t)n * m->P * 4, hipMemcpyDeviceToHost, ds.stream));
+        if (loss) GC_TRY_HIP(hipMemcpyAsync(loss, dl, (size_t)n * 4, hipMemcpyDeviceToHost, ds.stream));
+    }
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_tv(int nx, int ny, int nz, const uint8_t* mask, const float* u, int tv_dim, double scale,
+          double* R, float* dR, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    GC_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && u && R && (tv_dim == 2 || tv_dim == 3),
+               GC_E_INVAL, "bad arguments");
+    DeviceScope ds;
+    int rc;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    const int64_t G = (int64_t)nx * ny * nz;
+    const void *dm, *du;
+    if ((rc = stage_simple(sc, ds.mem_kind, mask, (size_t)G, &dm))) return rc;
+    if ((rc = stage_simple(sc, ds.mem_kind, u, (size_t)G * 4, &du))) return rc;
+    float* dd = dR;
+    if (dR && ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dd, (size_t)G));
+    const int64_t nblk = (G + kBlock - 1) / kBlock;
+    double *part = nullptr, *dsum = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&part, (size_t)nblk));
+    GC_TRY_HIP(sc.alloc_n(&dsum, 1));
+    GC_TRY_HIP(tv_grid(nx, ny, nz, (const uint8_t*)dm, (const float*)du, tv_dim, (float)scale, part,
+                       nblk, dd, ds.stream));
+    GC_TRY_HIP(sum_partials_f64(part, nblk, dsum, ds.stream));
+    GC_TRY_HIP(hipMemcpyAsync(R, dsum, sizeof(double), hipMemcpyDeviceToHost, ds.stream));
+    if (dR && ds.mem_kind == GC_MEM_HOST)
+        GC_TRY_HIP(hipMemcpyAsync(dR, dd, (size_t)G * 4, hipMemcpyDeviceToHost, ds.stream));
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    GC_REQUIRE(ctr && out && n >= 0, GC_E_INVAL, "bad arguments");
+    DeviceScope ds;
+    int rc;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    const void* dc;
+    if ((rc = stage_simple(sc, ds.mem_kind, ctr, (size_t)n * 16, &dc))) return rc;
+    uint32_t* dout = out;
+    if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dout, (size_t)std::max<int64_t>(n, 1) * 4));
+    GC_TRY_HIP(philox_batch(seed, (const uint32_t*)dc, n, dout, ds.stream));
+    if (ds.mem_kind == GC_MEM_HOST && n)
+        GC_TRY_HIP(hipMemcpyAsync(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost, ds.stream));
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_philox_uniform_normal(uint64_t seed, const uint32_t* ctr, int64_t n, int precision,
+                             void* out_u, void* out_z, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    GC_REQUIRE(ctr && out_u && out_z && n >= 0 && (precision == 0 || precision == 1), GC_E_INVAL,
+               "bad arguments");
+    DeviceScope ds;
+    int rc;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    const void* dc;
+    if ((rc = stage_simple(sc, ds.mem_kind, ctr, (size_t)n * 16, &dc))) return rc;
+    const size_t es = precision ? 8 : 4;
+    void *du = out_u, *dz = out_z;
+    if (ds.mem_kind == GC_MEM_HOST) {
+        GC_TRY_HIP(sc.alloc(&du, (size_t)std::max<int64_t>(n, 1) * 4 * es));
+        GC_TRY_HIP(sc.alloc(&dz, (size_t)std::max<int64_t>(n, 1) * 4 * es));
+    }
+    GC_TRY_HIP(philox_uniform_normal(seed, (const uint32_t*)dc, n, precision == 1, du, dz, ds.stream));
+    if (ds.mem_kind == GC_MEM_HOST && n) {
+        GC_TRY_HIP(hipMemcpyAsync(out_u, du, (size_t)n * 4 * es, hipMemcpyDeviceToHost, ds.stream));
+        GC_TRY_HIP(hipMemcpyAsync(out_z, dz, (size_t)n * 4 * es, hipMemcpyDeviceToHost, ds.stream));
+    }
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+}  // extern "C"

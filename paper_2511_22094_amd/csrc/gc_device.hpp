@@ -1,0 +1,541 @@
+// Device-side building blocks of the voxel-parallel fitting path:
+// precision traits, the counter-based random stream, and the forward
+// models of the registry with their hand-written adjoints.
+//
+// Everything here is instantiated twice: Real = float is the production
+// path (fast hardware transcendentals, recurrences over uniformly spaced
+// echoes), Real = double is the deterministic test path that mirrors the
+// FP64 definition step by step.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gc {
+
+constexpr int kMaxP = 9;          // widest model (3-pool GRE)
+constexpr int kBlock = 256;       // threads per block for every voxel kernel
+
+enum ModelKind { MONOEXP_T2S = 0, MONOEXP_R2S = 1, GRE3 = 2, DWI2 = 3, LINEAR3 = 4 };
+
+// --------------------------------------------------------------------------
+// Precision traits.  FP32 uses the hardware transcendental unit directly:
+// v_exp_f32 / v_log_f32 work in base 2, v_sin_f32 / v_cos_f32 take their
+// argument in revolutions (sin(2 pi x)), which is exactly the form the
+// Box-Muller angle and the GRE phase 2 pi df TE already have.
+// --------------------------------------------------------------------------
+template <typename R> struct Math;
+
+template <> struct Math<float> {
+    static __device__ __forceinline__ float exp(float x) {
+        return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+    }
+    static __device__ __forceinline__ float ln(float x) {
+        return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+    }
+    static __device__ __forceinline__ float sin2pi(float rev) {
+        return __builtin_amdgcn_sinf(rev);
+    }
+    static __device__ __forceinline__ float cos2pi(float rev) {
+        return __builtin_amdgcn_cosf(rev);
+    }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    // -2 ln(u) for Box-Muller, straight from the base-2 logarithm
+    static __device__ __forceinline__ float m2ln(float u) {
+        return __builtin_amdgcn_logf(u) * -1.38629436111989062f;
+    }
+    // sine / cosine of an angle in radians
+    static __device__ __forceinline__ float sin(float x) {
+        return __builtin_amdgcn_sinf(x * 0.159154943091895336f);
+    }
+    static __device__ __forceinline__ float cos(float x) {
+        return __builtin_amdgcn_cosf(x * 0.159154943091895336f);
+    }
+};
+
+template <> struct Math<double> {
+    static constexpr double kTwoPi = 6.28318530717958647692;
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double ln(double x) { return ::log(x); }
+    static __device__ __forceinline__ double sin2pi(double rev) { return ::sin(kTwoPi * rev); }
+    static __device__ __forceinline__ double cos2pi(double rev) { return ::cos(kTwoPi * rev); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double m2ln(double u) { return -2.0 * ::log(u); }
+    static __device__ __forceinline__ double sin(double x) { return ::sin(x); }
+    static __device__ __forceinline__ double cos(double x) { return ::cos(x); }
+};
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11).  The key (the job's seed) is the
+// same for every lane, so the key schedule stays in scalar registers; each
+// round costs two 32x32->64 multiplies and two three-way XORs per lane.
+// --------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        uint32_t nx = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        uint32_t nz = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        c.y = (uint32_t)p1;
+        c.w = (uint32_t)p0;
+        c.x = nx;
+        c.z = nz;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// (2k+1) / 2^24 from the top 23 bits: exact in both precisions, in (0,1).
+template <typename R> __device__ __forceinline__ R uniform01(uint32_t w) {
+    return ((R)(w >> 9) + (R)0.5) * (R)1.1920928955078125e-07;   // 2^-23
+}
+
+// Draws of one MH step: P normals (Box-Muller on consecutive word pairs) and
+// the acceptance uniform (the word after the last pair).  Counter =
+// (voxel, chain | purpose << 16, iteration, block).
+template <int P> struct StepDraws {
+    static constexpr int kPairs = (P + 1) / 2;
+    static constexpr int kWords = 2 * kPairs + 1;
+    static constexpr int kBlocks = (kWords + 3) / 4;
+};
+
+template <typename R, int P>
+__device__ __forceinline__ void mh_draws(uint32_t v, uint32_t c, uint32_t t, uint32_t k0,
+                                         uint32_t k1, R (&z)[P], R& u_acc) {
+    constexpr int NB = StepDraws<P>::kBlocks;
+    uint32_t w[4 * NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        U4 o = philox4x32_10(U4{v, c, t, (uint32_t)b}, k0, k1);
+        w[4 * b + 0] = o.x;
+        w[4 * b + 1] = o.y;
+        w[4 * b + 2] = o.z;
+        w[4 * b + 3] = o.w;
+    }
+#pragma unroll
+    for (int i = 0; i < StepDraws<P>::kPairs; ++i) {
+        R u1 = uniform01<R>(w[2 * i]);
+        R u2 = uniform01<R>(w[2 * i + 1]);
+        R r = Math<R>::sqrt(Math<R>::m2ln(u1));
+        if (2 * i < P) z[2 * i] = r * Math<R>::cos2pi(u2);
+        if (2 * i + 1 < P) z[2 * i + 1] = r * Math<R>::sin2pi(u2);
+    }
+    u_acc = uniform01<R>(w[StepDraws<P>::kWords - 1]);
+}
+
+// --------------------------------------------------------------------------
+// Acquisition as seen by the kernels (device pointers, uniform across lanes).
+// TE in ms; b already multiplied by 1e-3 (so b*D is dimensionless with D in
+// um^2/ms); bvec [M][3].  `uniform` marks equally spaced echoes te0 + m*dte,
+// which lets the FP32 path replace per-echo exponentials by recurrences.
+// --------------------------------------------------------------------------
+struct AcqDev {
+    const float* te;
+    const float* bval;
+    const float* bvec;
+    const double* te_d;
+    const double* bval_d;
+    const double* bvec_d;
+    int M;
+    int uniform;
+    float te0, dte;
+    double te0_d, dte_d;
+};
+
+template <typename R> struct AcqView;
+template <> struct AcqView<float> {
+    static __device__ __forceinline__ float te(const AcqDev& a, int m) { return a.te[m]; }
+    static __device__ __forceinline__ float b(const AcqDev& a, int m) { return a.bval[m]; }
+    static __device__ __forceinline__ float g(const AcqDev& a, int m, int k) {
+        return a.bvec[3 * m + k];
+    }
+    static __device__ __forceinline__ float te0(const AcqDev& a) { return a.te0; }
+    static __device__ __forceinline__ float dte(const AcqDev& a) { return a.dte; }
+};
+template <> struct AcqView<double> {
+    static __device__ __forceinline__ double te(const AcqDev& a, int m) { return a.te_d[m]; }
+    static __device__ __forceinline__ double b(const AcqDev& a, int m) { return a.bval_d[m]; }
+    static __device__ __forceinline__ double g(const AcqDev& a, int m, int k) {
+        return a.bvec_d[3 * m + k];
+    }
+    static __device__ __forceinline__ double te0(const AcqDev& a) { return a.te0_d; }
+    static __device__ __forceinline__ double dte(const AcqDev& a) { return a.dte_d; }
+};
+
+// Recurrences over echoes are used only in FP32 with equally spaced echoes;
+// FP64 always evaluates the closed forms echo by echo.
+template <typename R> struct UseRecur { static constexpr bool value = false; };
+template <> struct UseRecur<float> { static constexpr bool value = true; };
+
+// A measurement loop bound: compile-time MAXM > 0 fully unrolls (measured
+// data can then live in registers); MAXM == 0 is a runtime loop.
+#define GC_FOR_MEAS(m, MAXM, M)                                                 \
+    _Pragma("unroll") for (int m = 0; m < ((MAXM) > 0 ? (MAXM) : (M)); ++m)    \
+        if ((MAXM) == 0 || m < (M))
+
+// --------------------------------------------------------------------------
+// Forward models.  Each provides
+//   sse<MAXM>(th, Y, a)          sum_j (y_j - s_j)^2            (MH path)
+//   grad<MAXM>(th, Y, D, a, g)   g = J^T d with d_j = D(j, s_j)  (fits, VJP)
+//   forward(th, a, S)            S(j, s_j) for every component
+// Y.re(m) / Y.im(m) return the measured real / imaginary part of
+// measurement m (real models use .re only); D.re(m, s) / D.im(m, s) return
+// dLoss/ds for that component (and may accumulate the loss itself); S.re /
+// S.im receive forward values.  Component order in memory is the M real
+// parts, then the M imaginary parts.
+// --------------------------------------------------------------------------
+
+// s = S0 exp(k TE) with k = -1/T2* (monoexp_t2s) or -R2* 1e-3 (monoexp_r2s)
+template <typename R, int KIND> struct MonoExp {
+    static constexpr int P = 2;
+    static constexpr bool kComplex = false;
+    static __device__ __forceinline__ R rate(const R* th) {
+        if (KIND == MONOEXP_T2S) return -Math<R>::rcp(th[1]);
+        return -th[1] * (R)1e-3;
+    }
+    template <int MAXM, class Y>
+    static __device__ __forceinline__ R sse(const R* th, const Y& y, const AcqDev& a) {
+        R k = rate(th);
+        R acc0 = 0, acc1 = 0;
+        if (UseRecur<R>::value && a.uniform) {
+            R e = th[0] * Math<R>::exp(k * AcqView<R>::te0(a));
+            R q = Math<R>::exp(k * AcqView<R>::dte(a));
+            GC_FOR_MEAS(m, MAXM, a.M) {
+                R r = (R)y.re(m) - e;
+                if (m & 1) acc1 += r * r; else acc0 += r * r;
+                e *= q;
+            }
+        } else {
+            GC_FOR_MEAS(m, MAXM, a.M) {
+                R r = (R)y.re(m) - th[0] * Math<R>::exp(k * AcqView<R>::te(a, m));
+                if (m & 1) acc1 += r * r; else acc0 += r * r;
+            }
+        }
+        return acc0 + acc1;
+    }
+    template <int MAXM, class D>
+    static __device__ __forceinline__ void grad(const R* th, D& d, const AcqDev& a, R* g) {
+        R k = rate(th);
+        R gs = 0, gk = 0;   // gk accumulates sum d * s * TE
+        GC_FOR_MEAS(m, MAXM, a.M) {
+            R te = AcqView<R>::te(a, m);
+            R E = Math<R>::exp(k * te);
+            R s = th[0] * E;
+            R dj = d.re(m, s);
+            gs += dj * E;
+            gk += dj * s * te;
+        }
+        g[0] = gs;
+        // ds/dT2 = S0 E TE / T2^2 ; ds/dR2 = -S0 E TE 1e-3
+        if (KIND == MONOEXP_T2S) g[1] = gk * (k * k);
+        else g[1] = -gk * (R)1e-3;
+    }
+    template <class S>
+    static __device__ __forceinline__ void forward(const R* th, const AcqDev& a, S& out) {
+        R k = rate(th);
+        for (int m = 0; m < a.M; ++m) out.re(m, th[0] * Math<R>::exp(k * AcqView<R>::te(a, m)));
+    }
+};
+
+// s = sum_k A_k exp(-TE / tau_k), tau = (10, 30, 80) ms: linear in A.
+template <typename R> struct Linear3 {
+    static constexpr int P = 3;
+    static constexpr bool kComplex = false;
+    static __device__ __forceinline__ R rk(int k) {
+        return k == 0 ? (R)(-1.0 / 10.0) : (k == 1 ? (R)(-1.0 / 30.0) : (R)(-1.0 / 80.0));
+    }
+    template <int MAXM, class Y>
+    static __device__ __forceinline__ R sse(const R* th, const Y& y, const AcqDev& a) {
+        R acc = 0;
+        GC_FOR_MEAS(m, MAXM, a.M) {
+            R te = AcqView<R>::te(a, m);
+            R s = th[0] * Math<R>::exp(rk(0) * te) + th[1] * Math<R>::exp(rk(1) * te) +
+                  th[2] * Math<R>::exp(rk(2) * te);
+            R r = (R)y.re(m) - s;
+            acc += r * r;
+        }
+        return acc;
+    }
+    template <int MAXM, class D>
+    static __device__ __forceinline__ void grad(const R* th, D& d, const AcqDev& a, R* g) {
+        g[0] = g[1] = g[2] = 0;
+        GC_FOR_MEAS(m, MAXM, a.M) {
+            R te = AcqView<R>::te(a, m);
+            R e0 = Math<R>::exp(rk(0) * te), e1 = Math<R>::exp(rk(1) * te),
+              e2 = Math<R>::exp(rk(2) * te);
+            R dj = d.re(m, th[0] * e0 + th[1] * e1 + th[2] * e2);
+            g[0] += dj * e0;
+            g[1] += dj * e1;
+            g[2] += dj * e2;
+        }
+    }
+    template <class S>
+    static __device__ __forceinline__ void forward(const R* th, const AcqDev& a, S& out) {
+        for (int m = 0; m < a.M; ++m) {
+            R te = AcqView<R>::te(a, m);
+            out.re(m, th[0] * Math<R>::exp(rk(0) * te) + th[1] * Math<R>::exp(rk(1) * te) +
+                       th[2] * Math<R>::exp(rk(2) * te));
+        }
+    }
+};
+
+// Three-pool complex GRE: s = sum_k A_k exp(-TE/T2_k) exp(i 2 pi df_k TE 1e-3).
+// Pool term u_k(TE) = exp(-TE/T2_k + i 2 pi df_k TE 1e-3) (unit amplitude).
+// With equally spaced echoes, u_k(TE + dte) = u_k(TE) q_k: one complex
+// multiply per echo and pool instead of exp + sin + cos.
+template <typename R> struct Gre3 {
+    static constexpr int P = 9;
+    static constexpr bool kComplex = true;
+
+    // per-pool decay rate -1/T2 and phase rate df 1e-3 (revolutions per ms)
+    static __device__ __forceinline__ void rates(const R* th, R* kr, R* kp) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            kr[k] = -Math<R>::rcp(th[3 + k]);
+            kp[k] = th[6 + k] * (R)1e-3;
+        }
+    }
+    static __device__ __forceinline__ void cexp(R re_exp, R rev, R& cr, R& ci) {
+        R mag = Math<R>::exp(re_exp);
+        cr = mag * Math<R>::cos2pi(rev);
+        ci = mag * Math<R>::sin2pi(rev);
+    }
+
+    template <int MAXM, class Y>
+    static __device__ __forceinline__ R sse(const R* th, const Y& y, const AcqDev& a) {
+        R kr[3], kp[3];
+        rates(th, kr, kp);
+        R accr = 0, acci = 0;
+        if (UseRecur<R>::value && a.uniform) {
+            R te0 = AcqView<R>::te0(a), dte = AcqView<R>::dte(a);
+            R zr[3], zi[3], qr[3], qi[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cexp(kr[k] * te0, kp[k] * te0, zr[k], zi[k]);
+                zr[k] *= th[k];
+                zi[k] *= th[k];
+                cexp(kr[k] * dte, kp[k] * dte, qr[k], qi[k]);
+            }
+            GC_FOR_MEAS(m, MAXM, a.M) {
+                R sr = zr[0] + zr[1] + zr[2];
+                R si = zi[0] + zi[1] + zi[2];
+                R rr = (R)y.re(m) - sr;
+                R ri = (R)y.im(m) - si;
+                accr += rr * rr;
+                acci += ri * ri;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    R nr = zr[k] * qr[k] - zi[k] * qi[k];
+                    R ni = zr[k] * qi[k] + zi[k] * qr[k];
+                    zr[k] = nr;
+                    zi[k] = ni;
+                }
+            }
+        } else {
+            GC_FOR_MEAS(m, MAXM, a.M) {
+                R te = AcqView<R>::te(a, m);
+                R sr = 0, si = 0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    R cr, ci;
+                    cexp(kr[k] * te, kp[k] * te, cr, ci);
+                    sr += th[k] * cr;
+                    si += th[k] * ci;
+                }
+                R rr = (R)y.re(m) - sr;
+                R ri = (R)y.im(m) - si;
+                accr += rr * rr;
+                acci += ri * ri;
+            }
+        }
+        return accr + acci;
+    }
+
+    template <int MAXM, class D>
+    static __device__ __forceinline__ void grad(const R* th, D& d, const AcqDev& a, R* g) {
+        R kr[3], kp[3];
+        rates(th, kr, kp);
+        R gA[3] = {0, 0, 0}, gT[3] = {0, 0, 0}, gF[3] = {0, 0, 0};
+        const bool rec = UseRecur<R>::value && a.uniform;
+        R ur[3], ui[3], qr[3], qi[3];
+        if (rec) {
+            R te0 = AcqView<R>::te0(a), dte = AcqView<R>::dte(a);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cexp(kr[k] * te0, kp[k] * te0, ur[k], ui[k]);
+                cexp(kr[k] * dte, kp[k] * dte, qr[k], qi[k]);
+            }
+        }
+        GC_FOR_MEAS(m, MAXM, a.M) {
+            R te = AcqView<R>::te(a, m);
+            if (!rec) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cexp(kr[k] * te, kp[k] * te, ur[k], ui[k]);
+            }
+            R sr = th[0] * ur[0] + th[1] * ur[1] + th[2] * ur[2];
+            R si = th[0] * ui[0] + th[1] * ui[1] + th[2] * ui[2];
+            R dr = d.re(m, sr);
+            R di = d.im(m, si);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                R p = dr * ur[k] + di * ui[k];     // Re(conj(d) u_k)
+                R q = di * ur[k] - dr * ui[k];     // Re(conj(d) i u_k)
+                gA[k] += p;
+                gT[k] += p * te;
+                gF[k] += q * te;
+            }
+            if (rec) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    R nr = ur[k] * qr[k] - ui[k] * qi[k];
+                    R ni = ur[k] * qi[k] + ui[k] * qr[k];
+                    ur[k] = nr;
+                    ui[k] = ni;
+                }
+            }
+        }
+        const R w = (R)6.283185307179586477e-3;   // 2 pi 1e-3
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            g[k] = gA[k];
+            g[3 + k] = gT[k] * th[k] * (kr[k] * kr[k]);   // A TE / T2^2
+            g[6 + k] = gF[k] * th[k] * w;
+        }
+    }
+    template <class S>
+    static __device__ __forceinline__ void forward(const R* th, const AcqDev& a, S& out) {
+        R kr[3], kp[3];
+        rates(th, kr, kp);
+        for (int m = 0; m < a.M; ++m) {
+            R te = AcqView<R>::te(a, m);
+            R sr = 0, si = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                R cr, ci;
+                cexp(kr[k] * te, kp[k] * te, cr, ci);
+                sr += th[k] * cr;
+                si += th[k] * ci;
+            }
+            out.re(m, sr);
+            out.im(m, si);
+        }
+    }
+};
+
+// Stick + ball diffusion: s = f exp(-b Da (g.n)^2) + (1-f) exp(-b De),
+// n = (sin th cos ph, sin th sin ph, cos th), b pre-scaled by 1e-3.
+template <typename R> struct Dwi2 {
+    static constexpr int P = 5;
+    static constexpr bool kComplex = false;
+    static __device__ __forceinline__ void dir(const R* th, R* n) {
+        R st = Math<R>::sin(th[3]), ct = Math<R>::cos(th[3]);
+        R sp = Math<R>::sin(th[4]), cp = Math<R>::cos(th[4]);
+        n[0] = st * cp;
+        n[1] = st * sp;
+        n[2] = ct;
+        n[3] = ct * cp;   // dn/dtheta
+        n[4] = ct * sp;
+        n[5] = -st;
+        n[6] = -st * sp;  // dn/dphi (z component 0)
+        n[7] = st * cp;
+    }
+    template <int MAXM, class Y>
+    static __device__ __forceinline__ R sse(const R* th, const Y& y, const AcqDev& a) {
+        R n[8];
+        dir(th, n);
+        R acc = 0;
+        GC_FOR_MEAS(m, MAXM, a.M) {
+            R x = AcqView<R>::g(a, m, 0) * n[0] + AcqView<R>::g(a, m, 1) * n[1] +
+                  AcqView<R>::g(a, m, 2) * n[2];
+            R b = AcqView<R>::b(a, m);
+            R s = th[0] * Math<R>::exp(-b * th[1] * x * x) +
+                  ((R)1 - th[0]) * Math<R>::exp(-b * th[2]);
+            R r = (R)y.re(m) - s;
+            acc += r * r;
+        }
+        return acc;
+    }
+    template <int MAXM, class D>
+    static __device__ __forceinline__ void grad(const R* th, D& d, const AcqDev& a, R* g) {
+        R n[8];
+        dir(th, n);
+        R gf = 0, gda = 0, gde = 0, gn0 = 0, gn1 = 0, gn2 = 0;
+        GC_FOR_MEAS(m, MAXM, a.M) {
+            R g0 = AcqView<R>::g(a, m, 0), g1 = AcqView<R>::g(a, m, 1),
+              g2 = AcqView<R>::g(a, m, 2);
+            R b = AcqView<R>::b(a, m);
+            R x = g0 * n[0] + g1 * n[1] + g2 * n[2];
+            R Ea = Math<R>::exp(-b * th[1] * x * x);
+            R Ee = Math<R>::exp(-b * th[2]);
+            R dj = d.re(m, th[0] * Ea + ((R)1 - th[0]) * Ee);
+            gf += dj * (Ea - Ee);
+            R t = dj * b * Ea;      // d * b * Ea
+            gda += t * x * x;
+            gde += dj * b * Ee;
+            R tx = t * x;
+            gn0 += tx * g0;
+            gn1 += tx * g1;
+            gn2 += tx * g2;
+        }
+        g[0] = gf;
+        g[1] = -th[0] * gda;
+        g[2] = -((R)1 - th[0]) * gde;
+        R c = (R)-2 * th[0] * th[1];
+        g[3] = c * (gn0 * n[3] + gn1 * n[4] + gn2 * n[5]);
+        g[4] = c * (gn0 * n[6] + gn1 * n[7]);
+    }
+    template <class S>
+    static __device__ __forceinline__ void forward(const R* th, const AcqDev& a, S& out) {
+        R n[8];
+        dir(th, n);
+        for (int m = 0; m < a.M; ++m) {
+            R x = AcqView<R>::g(a, m, 0) * n[0] + AcqView<R>::g(a, m, 1) * n[1] +
+                  AcqView<R>::g(a, m, 2) * n[2];
+            R b = AcqView<R>::b(a, m);
+            out.re(m, th[0] * Math<R>::exp(-b * th[1] * x * x) +
+                       ((R)1 - th[0]) * Math<R>::exp(-b * th[2]));
+        }
+    }
+};
+
+template <int KIND, typename R> struct ModelOf;
+template <typename R> struct ModelOf<MONOEXP_T2S, R> { using T = MonoExp<R, MONOEXP_T2S>; };
+template <typename R> struct ModelOf<MONOEXP_R2S, R> { using T = MonoExp<R, MONOEXP_R2S>; };
+template <typename R> struct ModelOf<GRE3, R> { using T = Gre3<R>; };
+template <typename R> struct ModelOf<DWI2, R> { using T = Dwi2<R>; };
+template <typename R> struct ModelOf<LINEAR3, R> { using T = Linear3<R>; };
+
+// Effective measurement count for register arrays sized at compile time.
+template <int KIND, int MAXM> struct MeasEff {
+    static constexpr int value = (KIND == GRE3 ? 2 * MAXM : MAXM);
+};
+
+// --------------------------------------------------------------------------
+// Wave / block reductions (wave64).
+// --------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over a block of kBlock threads in a fixed order; result valid in thread 0.
+template <typename T> __device__ __forceinline__ T block_sum(T v, T* lds /*[kBlock/64]*/) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    T r = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) r += lds[i];
+    }
+    return r;
+}
+
+}  // namespace gc

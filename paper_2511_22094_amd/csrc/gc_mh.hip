@@ -1,0 +1,330 @@
+// Fused Metropolis-Hastings kernels (paper §2.2.2): one lane per (voxel,
+// chain).  A launch runs a chunk of iterations entirely in registers --
+// random draws, proposal, bounds test, forward model, likelihood, accept /
+// reject, retention and FP64 Welford moments -- and leaves the chain state
+// in HBM for the next chunk.  The same kernels serve one job or many (the
+// block work-list maps blocks to jobs).
+#include "gc_internal.hpp"
+
+namespace gc {
+
+namespace {
+
+// measured data held in registers (compile-time indices only)
+template <int MAXM, bool CPLX> struct YReg {
+    float r[MAXM];
+    float i[CPLX ? MAXM : 1];
+    __device__ __forceinline__ float re(int m) const { return r[m]; }
+    __device__ __forceinline__ float im(int m) const { return i[CPLX ? m : 0]; }
+};
+
+// measured data read from HBM (any measurement count)
+struct YGlob {
+    const float* y;
+    int64_t n;
+    int64_t v;
+    int M;
+    __device__ __forceinline__ float re(int m) const { return y[(int64_t)m * n + v]; }
+    __device__ __forceinline__ float im(int m) const { return y[(int64_t)(M + m) * n + v]; }
+};
+
+template <typename R> __device__ __forceinline__ R lbR(const MhJob& J, int p);
+template <> __device__ __forceinline__ float lbR<float>(const MhJob& J, int p) { return J.lb[p]; }
+template <> __device__ __forceinline__ double lbR<double>(const MhJob& J, int p) { return J.lbd[p]; }
+template <typename R> __device__ __forceinline__ R ubR(const MhJob& J, int p);
+template <> __device__ __forceinline__ float ubR<float>(const MhJob& J, int p) { return J.ub[p]; }
+template <> __device__ __forceinline__ double ubR<double>(const MhJob& J, int p) { return J.ubd[p]; }
+template <typename R> __device__ __forceinline__ R stepR(const MhJob& J, int p);
+template <> __device__ __forceinline__ float stepR<float>(const MhJob& J, int p) { return J.step[p]; }
+template <> __device__ __forceinline__ double stepR<double>(const MhJob& J, int p) { return J.stepd[p]; }
+template <typename R> __device__ __forceinline__ R x0R(const MhJob& J, int p);
+template <> __device__ __forceinline__ float x0R<float>(const MhJob& J, int p) { return J.x0c[p]; }
+template <> __device__ __forceinline__ double x0R<double>(const MhJob& J, int p) { return J.x0cd[p]; }
+template <typename R> __device__ __forceinline__ R inv2s2R(const MhJob& J);
+template <> __device__ __forceinline__ float inv2s2R<float>(const MhJob& J) { return J.inv2s2; }
+template <> __device__ __forceinline__ double inv2s2R<double>(const MhJob& J) { return J.inv2s2d; }
+
+// First iteration t >= max(t0, burnin) with (t - burnin + 1) % thin == 0.
+__device__ __forceinline__ int first_keep(int t0, int burnin, int thin) {
+    int t = t0 > burnin ? t0 : burnin;
+    int r = (t - burnin + 1) % thin;
+    return r == 0 ? t : t + (thin - r);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// Initial state: midpoint / given constant, uniform in the box (Philox with
+// purpose 1, iteration 0), or a per-voxel map; log-likelihood of the start.
+// --------------------------------------------------------------------------
+template <int KIND, typename R>
+__global__ __launch_bounds__(kBlock) void mh_init_kernel(const MhJob* __restrict__ jobs,
+                                                        const BlkMap* __restrict__ map) {
+    using Mdl = typename ModelOf<KIND, R>::T;
+    constexpr int P = Mdl::P;
+    const BlkMap bm = map[blockIdx.x];
+    const MhJob& J = jobs[bm.job];
+    const int64_t n = J.n, NL = n * J.C;
+    const int64_t L = bm.lane0 + threadIdx.x;
+    if (L >= NL) return;
+    const int64_t v = L % n;
+    const int c = (int)(L / n);
+    R th[P];
+    if (J.x0_mode == 1) {
+#pragma unroll
+        for (int b = 0; b < (P + 3) / 4; ++b) {
+            U4 o = philox4x32_10(U4{(uint32_t)v, (uint32_t)c | (1u << 16), 0u, (uint32_t)b},
+                                 J.k0, J.k1);
+            uint32_t w[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int p = 4 * b + i;
+                if (p < P)
+                    th[p] = lbR<R>(J, p) + (ubR<R>(J, p) - lbR<R>(J, p)) * uniform01<R>(w[i]);
+            }
+        }
+    } else if (J.x0map) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) th[p] = (R)J.x0map[(int64_t)p * n + v];
+    } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p) th[p] = x0R<R>(J, p);
+    }
+    const R w = J.w ? (R)J.w[v] : (R)1;
+    YGlob y{J.y, n, v, J.acq.M};
+    const R ll = -(inv2s2R<R>(J) * w * w) * Mdl::template sse<0>(th, y, J.acq);
+    R* TH = (R*)J.th;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        TH[(int64_t)p * NL + L] = th[p];
+        if (J.mean) {
+            J.mean[(int64_t)p * NL + L] = 0.0;
+            J.m2[(int64_t)p * NL + L] = 0.0;
+        }
+    }
+    ((R*)J.ll)[L] = ll;
+    J.acc[L] = 0;
+}
+
+// --------------------------------------------------------------------------
+// A chunk of MH iterations [t0, t1) for every (voxel, chain) lane.
+// --------------------------------------------------------------------------
+template <int KIND, typename R, int MAXM>
+__global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restrict__ jobs,
+                                                         const BlkMap* __restrict__ map) {
+    using Mdl = typename ModelOf<KIND, R>::T;
+    constexpr int P = Mdl::P;
+    constexpr bool CPLX = Mdl::kComplex;
+    const BlkMap bm = map[blockIdx.x];
+    const MhJob& J = jobs[bm.job];
+    const int64_t n = J.n, NL = n * J.C;
+    const int64_t L = bm.lane0 + threadIdx.x;
+    if (L >= NL) return;
+    const int64_t v = L % n;
+    const int c = (int)(L / n);
+    const AcqDev acq = J.acq;
+
+    // chain state
+    R* TH = (R*)J.th;
+    R th[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) th[p] = TH[(int64_t)p * NL + L];
+    R ll = ((R*)J.ll)[L];
+    int32_t acc = J.acc[L];
+    double mu[P], m2[P];
+    const bool welford = J.mean != nullptr;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        mu[p] = welford ? J.mean[(int64_t)p * NL + L] : 0.0;
+        m2[p] = welford ? J.m2[(int64_t)p * NL + L] : 0.0;
+    }
+    R lo[P], hi[P], st[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        lo[p] = lbR<R>(J, p);
+        hi[p] = ubR<R>(J, p);
+        st[p] = stepR<R>(J, p);
+    }
+    const R w = J.w ? (R)J.w[v] : (R)1;
+    const R nscale = -(inv2s2R<R>(J) * w * w);
+
+    // measured data
+    YReg<(MAXM > 0 ? MAXM : 1), CPLX> yr;
+    if constexpr (MAXM > 0) {
+#pragma unroll
+        for (int m = 0; m < MAXM; ++m) {
+            yr.r[m] = m < acq.M ? J.y[(int64_t)m * n + v] : 0.f;
+            if (CPLX) yr.i[m] = m < acq.M ? J.y[(int64_t)(acq.M + m) * n + v] : 0.f;
+        }
+    }
+    const YGlob yg{J.y, n, v, acq.M};
+
+    const int t0 = J.t0, t1 = J.t1, B = J.burnin, thin = J.thin;
+    int keep_t = first_keep(t0, B, thin);
+    const uint32_t vv = (uint32_t)v, cc = (uint32_t)c;
+    const uint32_t k0 = J.k0, k1 = J.k1;
+    for (int t = t0; t < t1; ++t) {
+        R z[P], u;
+        mh_draws<R, P>(vv, cc, (uint32_t)t, k0, k1, z, u);
+        R thp[P], the[P];
+        bool inb = true;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            thp[p] = th[p] + st[p] * z[p];
+            inb = inb && (thp[p] >= lo[p]) && (thp[p] <= hi[p]);
+        }
+        // out-of-box proposals are rejected; evaluate at the current state
+        // instead of branching so the wave stays converged
+#pragma unroll
+        for (int p = 0; p < P; ++p) the[p] = inb ? thp[p] : th[p];
+        R sse;
+        if constexpr (MAXM > 0) sse = Mdl::template sse<MAXM>(the, yr, acq);
+        else sse = Mdl::template sse<0>(the, yg, acq);
+        const R llp = nscale * sse;
+        const bool a = inb && (Math<R>::ln(u) < llp - ll);
+#pragma unroll
+        for (int p = 0; p < P; ++p) th[p] = a ? thp[p] : th[p];
+        ll = a ? llp : ll;
+        acc += a ? 1 : 0;
+        if (t == keep_t) {   // uniform across the job
+            keep_t += thin;
+            const int k = (t - B + 1) / thin;   // 1-based sample count of this chain
+            const double inv = 1.0 / (double)k;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double x = (double)th[p];
+                const double d = x - mu[p];
+                mu[p] += d * inv;
+                m2[p] += d * (x - mu[p]);
+            }
+            if (J.samples) {
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    J.samples[(((int64_t)c * J.K + (k - 1)) * P + p) * n + v] = (float)th[p];
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        TH[(int64_t)p * NL + L] = th[p];
+        if (welford) {
+            J.mean[(int64_t)p * NL + L] = mu[p];
+            J.m2[(int64_t)p * NL + L] = m2[p];
+        }
+    }
+    ((R*)J.ll)[L] = ll;
+    J.acc[L] = acc;
+}
+
+// --------------------------------------------------------------------------
+// Pool the chains of each voxel (equal sample counts K per chain):
+//   mean = average of chain means,
+//   M2   = sum of chain M2 + K sum_c (mean_c - mean)^2,  std = sqrt(M2/(C K - 1)).
+// vmap blocks cover voxels (not lanes); outputs are compacted [P][n].
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void mh_finalize_kernel(const MhJob* __restrict__ jobs,
+                                                            const BlkMap* __restrict__ vmap,
+                                                            double* __restrict__ out_mean,
+                                                            double* __restrict__ out_std) {
+    const BlkMap bm = vmap[blockIdx.x];
+    const MhJob& J = jobs[bm.job];
+    const int64_t n = J.n, NL = n * J.C;
+    const int64_t v = bm.lane0 + threadIdx.x;
+    if (v >= n) return;
+    const int C = J.C, K = J.K, P = J.P;
+    for (int p = 0; p < P; ++p) {
+        double s = 0.0;
+        for (int c = 0; c < C; ++c) s += J.mean[(int64_t)p * NL + (int64_t)c * n + v];
+        const double mean = s / (double)C;
+        double M2 = 0.0;
+        for (int c = 0; c < C; ++c) {
+            const double d = J.mean[(int64_t)p * NL + (int64_t)c * n + v] - mean;
+            M2 += J.m2[(int64_t)p * NL + (int64_t)c * n + v] + (double)K * d * d;
+        }
+        out_mean[(int64_t)p * n + v] = mean;
+        out_std[(int64_t)p * n + v] = sqrt(M2 / (double)(C * K - 1));
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+// Register-resident data sizes instantiated per model (measurement counts);
+// anything else runs the HBM-read variant (MAXM = 0).
+int mh_pick_maxm(int kind, int M) {
+    static const int mono[] = {12, 16, 32};
+    static const int gre[] = {12, 24, 32};
+    static const int dwi[] = {32, 64, 96};
+    const int* list = kind == GRE3 ? gre : (kind == DWI2 ? dwi : mono);
+    if (kind == LINEAR3) return M <= 12 ? 12 : (M <= 16 ? 16 : 0);
+    for (int i = 0; i < 3; ++i)
+        if (M <= list[i]) return list[i];
+    return 0;
+}
+
+template <int KIND, typename R>
+static hipError_t init_t(const MhJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((mh_init_kernel<KIND, R>), dim3(nblk), dim3(kBlock), 0, s, jobs, map);
+    return hipGetLastError();
+}
+
+hipError_t mh_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, int nblk,
+                   hipStream_t s) {
+#define GC_INIT(K)                                                              \
+    case K:                                                                     \
+        return fp64 ? init_t<K, double>(jobs, map, nblk, s) : init_t<K, float>(jobs, map, nblk, s);
+    switch (kind) {
+        GC_INIT(MONOEXP_T2S)
+        GC_INIT(MONOEXP_R2S)
+        GC_INIT(GRE3)
+        GC_INIT(DWI2)
+        GC_INIT(LINEAR3)
+    }
+#undef GC_INIT
+    return hipErrorInvalidValue;
+}
+
+template <int KIND, typename R, int MAXM>
+static hipError_t chunk_t(const MhJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((mh_chunk_kernel<KIND, R, MAXM>), dim3(nblk), dim3(kBlock), 0, s, jobs,
+                       map);
+    return hipGetLastError();
+}
+
+template <int KIND, int A, int B, int C>
+static hipError_t chunk_f32(int maxm, const MhJob* jobs, const BlkMap* map, int nblk,
+                            hipStream_t s) {
+    if (maxm == A) return chunk_t<KIND, float, A>(jobs, map, nblk, s);
+    if (maxm == B) return chunk_t<KIND, float, B>(jobs, map, nblk, s);
+    if (maxm == C) return chunk_t<KIND, float, C>(jobs, map, nblk, s);
+    return chunk_t<KIND, float, 0>(jobs, map, nblk, s);
+}
+
+hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkMap* map,
+                    int nblk, hipStream_t s) {
+    if (fp64) {
+        switch (kind) {
+            case MONOEXP_T2S: return chunk_t<MONOEXP_T2S, double, 0>(jobs, map, nblk, s);
+            case MONOEXP_R2S: return chunk_t<MONOEXP_R2S, double, 0>(jobs, map, nblk, s);
+            case GRE3: return chunk_t<GRE3, double, 0>(jobs, map, nblk, s);
+            case DWI2: return chunk_t<DWI2, double, 0>(jobs, map, nblk, s);
+            case LINEAR3: return chunk_t<LINEAR3, double, 0>(jobs, map, nblk, s);
+        }
+        return hipErrorInvalidValue;
+    }
+    switch (kind) {
+        case MONOEXP_T2S: return chunk_f32<MONOEXP_T2S, 12, 16, 32>(maxm, jobs, map, nblk, s);
+        case MONOEXP_R2S: return chunk_f32<MONOEXP_R2S, 12, 16, 32>(maxm, jobs, map, nblk, s);
+        case GRE3: return chunk_f32<GRE3, 12, 24, 32>(maxm, jobs, map, nblk, s);
+        case DWI2: return chunk_f32<DWI2, 32, 64, 96>(maxm, jobs, map, nblk, s);
+        case LINEAR3: return chunk_f32<LINEAR3, 12, 16, 16>(maxm, jobs, map, nblk, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t mh_finalize(bool /*fp64*/, const MhJob* jobs, const BlkMap* vmap, int nblk,
+                       double* out_mean, double* out_std, hipStream_t s) {
+    hipLaunchKernelGGL(mh_finalize_kernel, dim3(nblk), dim3(kBlock), 0, s, jobs, vmap, out_mean,
+                       out_std);
+    return hipGetLastError();
+}
+
+}  // namespace gc

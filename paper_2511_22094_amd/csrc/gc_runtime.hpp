@@ -1,0 +1,111 @@
+// Host runtime shared by the synchronous C ABI and the server: the model
+// object, error reporting, device / stream selection, stream-ordered
+// scratch memory, and the staging + compaction of one problem.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gacelle.h"
+#include "gc_internal.hpp"
+
+struct gc_model {
+    int kind = 0;
+    int P = 0;
+    int M = 0;
+    int Meff = 0;
+    bool complex_ = false;
+    std::string name;
+    std::vector<std::string> pnames;
+    std::vector<double> te, bval, bvec;   // host copies (bval in s/mm^2)
+    bool uniform = false;
+    double te0 = 0.0, dte = 0.0;
+    struct DevAcq {
+        void* buf = nullptr;              // one allocation holding all arrays
+        gc::AcqDev acq{};
+    };
+    mutable std::mutex mu;
+    mutable std::map<int, DevAcq> dev;    // per device ordinal
+};
+
+namespace gc {
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define GC_TRY_HIP(expr)                                                           \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::gc::set_error("%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                            __LINE__);                                             \
+            return GC_E_DEVICE;                                                    \
+        }                                                                          \
+    } while (0)
+
+#define GC_REQUIRE(cond, code, ...)      \
+    do {                                 \
+        if (!(cond)) {                   \
+            ::gc::set_error(__VA_ARGS__); \
+            return (code);               \
+        }                                \
+    } while (0)
+
+// Selects the device for the duration of a call and restores the previous one.
+struct DeviceScope {
+    int prev = -1;
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    int mem_kind = GC_MEM_HOST;
+    int open(const gc_exec* ex);
+    ~DeviceScope();
+};
+
+// Stream-ordered scratch allocations released at scope exit.
+struct Scratch {
+    hipStream_t s = nullptr;
+    std::vector<void*> ptrs;
+    explicit Scratch(hipStream_t st) : s(st) {}
+    ~Scratch();
+    hipError_t alloc(void** p, size_t bytes);
+    template <typename T> hipError_t alloc_n(T** p, size_t n) {
+        return alloc((void**)p, n * sizeof(T));
+    }
+};
+
+// Device-side acquisition of a model on the current device.
+int model_acq(const gc_model* m, int device, AcqDev* out);
+
+// A bulk argument in exec memory: returns a device pointer, staging host data.
+int stage_in(Scratch& sc, const void* p, size_t bytes, int mem_kind, const void** dptr);
+
+// Compaction of one volume (mask -> index maps, gathered rows).
+struct Packed {
+    int64_t G = 0, n = 0;
+    int32_t* g2c = nullptr;
+    int32_t* c2g = nullptr;
+    float* y = nullptr;      // [Meff][n]
+    float* w = nullptr;      // [n] or null
+    float* x0 = nullptr;     // [P][n] or null
+};
+int pack_problem(Scratch& sc, const gc_model* m, const gc_volume* data, const uint8_t* mask,
+                 const float* weights, const float* x0map, int mem_kind, Packed* out);
+
+int validate_bounds(const gc_model* m, const gc_bounds* b);
+int validate_volume(const gc_model* m, const gc_volume* v);
+
+// descriptor builders shared by the synchronous calls and the server
+int fill_mh_job(const gc_model* m, const gc_bounds* b, const gc_mcmc_hyper* h, int n_chains,
+                int n_iter, int burnin, int thin, const AcqDev& acq, MhJob* job);
+int fill_fit_job(const gc_model* m, const gc_bounds* b, const gc_adam_hyper* h, int64_t n,
+                 const AcqDev& acq, FitJob* job);
+
+void mempool_setup(int device);
+double now_seconds();
+
+}  // namespace gc

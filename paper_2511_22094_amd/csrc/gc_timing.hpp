@@ -1,0 +1,25 @@
+// Per-family kernel timing with HIP events (enabled by gc_timing_enable).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+namespace gc {
+
+bool timing_on();
+// Brackets launches: begin() before, end() after; flush() after the stream
+// has been synchronised adds the elapsed times to the family's total.
+struct LaunchTimer {
+    std::string family;
+    hipStream_t s;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    hipEvent_t pending = nullptr;
+    LaunchTimer(const char* fam, hipStream_t st) : family(fam), s(st) {}
+    void begin();
+    void end();
+    void flush();
+    ~LaunchTimer();
+};
+
+}  // namespace gc

@@ -243,7 +243,7 @@ def make_draw(model: str, shape, seed: int, sigma: float, acq: Optional[Acq] = N
         bnx = (nx + block - 1) // block
         ids = (z * bny + y) * bnx + x
         block_ids = ids[mask.astype(bool)]
-    truth = draw_truth(model, rng, n, block_ids)
+    truth = np.ascontiguousarray(draw_truth(model, rng, n, block_ids))
     me = meas_eff(model, acq.n_meas)
     noise = rng.standard_normal((me, n), dtype=np.float32)
     lb, ub = bounds(model)
@@ -297,7 +297,7 @@ CFG4_MCMC = dict(n_chains=8, n_iter=10000, burnin=1000, thin=10)
 # MH proposal widths (parameter units), chosen with the oracle for 20-50 %
 # acceptance at the workloads' noise levels and frozen here.
 MH_STEP: Dict[str, Tuple[float, ...]] = {
-    "monoexp_t2s": (0.006, 0.5),
+    "monoexp_t2s": (0.01, 1.0),
     "monoexp_r2s": (0.006, 0.3),
     "gre3": (0.01, 0.01, 0.01, 0.3, 1.0, 1.0, 0.5, 0.5, 0.5),
     "dwi2": (0.01, 0.02, 0.01, 0.02, 0.04),
