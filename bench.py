@@ -136,7 +136,88 @@ def adam_leg(g, torch, steps, warmup):
                 achieved_gbs=gbs, final_loss=r["final_loss"], n=n)
 
 
-def cpu_baseline(sample_vox=384):
+SERVE_MODELS = {
+    "monoexp_t2s": 0.01,
+    "gre3": 0.01,
+    "dwi2": 0.02,
+}
+
+
+def serve_trace_jobs(g, torch, n_jobs, vox_range, mcmc_iters, fit_iters, seed=3):
+    """Host-side job inputs of a serving trace (data made with the HIP forward)."""
+    from paper_2511_22094_amd import synth
+    trace = synth.serving_trace(seed, n_jobs, 20.0, vox_range, mcmc_iters, fit_iters)
+    acqs = {"monoexp_t2s": synth.Acq(te=synth.echo_times(2.0, 4.0, 12)),
+            "gre3": synth.Acq(te=synth.echo_times(2.0, 2.0, 24)),
+            "dwi2": synth.dwi_acq(np.random.default_rng(1002))}
+    models = {k: g.Model.from_acq(k, a) for k, a in acqs.items()}
+    jobs = []
+    for j in trace:
+        nx = 64
+        ny = (j.n_vox + nx - 1) // nx
+        mask = np.zeros((1, ny, nx), np.uint8)
+        mask.reshape(-1)[: j.n_vox] = 1
+        sigma = SERVE_MODELS[j.model]
+        d = synth.make_draw(j.model, (1, ny, nx), j.seed, sigma, acq=acqs[j.model], mask=mask,
+                            block=4 if j.model == "dwi2" else 0)
+        m = models[j.model]
+        s = g.gc_model_forward(m, torch.tensor(d.truth, dtype=torch.float32, device="cuda"))
+        y = (s + sigma * torch.from_numpy(d.noise).cuda()).cpu().numpy()
+        jobs.append((j, d, synth.scatter(y, mask), m))
+    return jobs
+
+
+def serve_run(g, jobs, baseline, saturated, chunk=256):
+    from paper_2511_22094_amd import synth
+    with g.Server(baseline=baseline, chunk_iters=chunk) as srv:
+        ids = []
+        t0 = time.perf_counter()
+        for j, d, y, m in jobs:
+            if not saturated:
+                wait = j.arrival_s - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+            if j.kind == "mcmc":
+                jid = srv.submit_mcmc(m, y, d.mask, d.lb, d.ub, j.n_chains, j.n_iter, j.burnin,
+                                      j.thin, sigma=d.sigma, step=synth.MH_STEP[j.model],
+                                      seed=j.seed, accept=False)
+                work = d.n * j.n_chains * j.n_iter
+            else:
+                tv = (0, 1, 2) if j.tv else ()
+                jid = srv.submit_fit(m, y, d.mask, d.lb, d.ub, n_iter=j.n_iter,
+                                     lam=1e-3 if j.tv else 0.0, tv_params=tv)
+                work = d.n * j.n_iter
+            ids.append((jid, work))
+        for jid, _ in ids:
+            srv.wait(jid)
+        span = time.perf_counter() - t0
+        st = srv.stats()
+    total = sum(w for _, w in ids)
+    return dict(makespan_s=span, value=total / span, p50_s=st["p50_latency_s"],
+                p99_s=st["p99_latency_s"], jobs=len(ids), voxel_iters=total)
+
+
+def serve_leg(g, torch, full=False):
+    if full:
+        jobs = serve_trace_jobs(g, torch, 256, (1e3, 1e6), (1000, 10000), (200, 500))
+    else:
+        jobs = serve_trace_jobs(g, torch, 64, (1e3, 1e5), (1000, 4000), (200, 500))
+    out = {}
+    for name, base, sat in (("batched", False, False), ("baseline", True, False),
+                            ("batched_saturated", False, True),
+                            ("baseline_saturated", True, True)):
+        log(f"bench: serving {name}")
+        out[name] = serve_run(g, jobs, base, sat)
+        log(f"bench:   {out[name]}")
+    out["speedup_saturated"] = (out["batched_saturated"]["value"] /
+                                out["baseline_saturated"]["value"])
+    out["trace"] = ("Poisson arrivals 20/s, %d jobs, models uniform over monoexp_t2s / gre3 / "
+                    "dwi2, voxels log-uniform in [%g, %g], 50/50 MCMC (1-8 chains) / Adam "
+                    "(TV on dwi2)" % (len(jobs), 1e3, 1e6 if full else 1e5))
+    return out
+
+
+def cpu_baseline(sample_vox=6144):
     """The FP64 oracle on a fixed voxel sample of the MH workload, all host threads."""
     import oracle
     from paper_2511_22094_amd import synth
@@ -164,6 +245,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adam", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving leg on the full 256-job trace (voxels up to 1e6)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -182,6 +266,9 @@ def main():
         adam = adam_leg(g, torch, args.steps, args.warmup)
         log(f"bench: Adam {adam['value']:.3e} voxel-iter/s, step kernel "
             f"{adam['per_launch_us']:.1f} us")
+    serve = None
+    if not args.no_serve:
+        serve = serve_leg(g, torch, args.serve_full)
     cpu = None
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
@@ -221,6 +308,8 @@ def main():
                                     "traffic": None,
                                     "bytes_per_voxel_iter": BYTES_PER_ADAM_TV_VOXEL_ITER,
                                     "launch_us": adam["per_launch_us"]}}
+    if serve is not None:
+        out["serving"] = serve
     print(json.dumps(out))
 
 

@@ -695,10 +695,10 @@ int orc_logl(int model, int M, const double *te, const double *bval, const doubl
  * floor(u0 K/2), word 1 -> z = ((a-1) u1 + 1)^2 / a (density ~ 1/sqrt(z) on
  * [1/a, a]), word 2 -> acceptance uniform; Y = X_j + z (X_k - X_j); outside
  * the box -> reject; accept iff log u2 < (P-1) log z + logL(Y) - logL(X_k).
- * Walkers start at x0 plus 1 % of the box width times a standard normal
- * (counter (v, k | 1 << 16, 0, b), Box-Muller on word pairs), clamped to the
- * box; x0_mode 1 starts them uniformly in the box.  Retention and moments
- * as for MH, with walkers in place of chains.
+ * Walkers start uniformly in [x0 - r, x0 + r], r = 1 % of the box width
+ * (x = x0 + r (2u - 1) with u = word p % 4 of counter (v, k | 1 << 16, 0,
+ * p / 4)), clamped to the box; x0_mode 1 starts them uniformly in the box.
+ * Retention and moments as for MH, with walkers in place of chains.
  * ------------------------------------------------------------------------ */
 int orc_ensemble(int model, int M, const double *te, const double *bval, const double *bvec,
                  int64_t n, const float *y, const float *w, const uint32_t *vidx,
@@ -734,20 +734,12 @@ int orc_ensemble(int model, int M, const double *te, const double *bval, const d
                 if (x0_mode == 1) {
                     orc_init_uniform(seed, v, (uint32_t)k, P, lb, ub, X + k * P);
                 } else {
-                    for (int b = 0; b < (P + 3) / 4; ++b) {
-                        uint32_t ctr[4] = {v, (uint32_t)k | (1u << 16), 0u, (uint32_t)b}, o[4];
+                    for (int p = 0; p < P; ++p) {
+                        uint32_t ctr[4] = {v, (uint32_t)k | (1u << 16), 0u, (uint32_t)(p / 4)}, o[4];
                         orc_philox4x32_10(ctr, key, o);
-                        for (int pr = 0; pr < 2; ++pr) {
-                            double z0, z1;
-                            orc_box_muller(orc_uniform(o[2 * pr]), orc_uniform(o[2 * pr + 1]), &z0, &z1);
-                            double zz[2] = {z0, z1};
-                            for (int q = 0; q < 2; ++q) {
-                                int p = 4 * b + 2 * pr + q;
-                                if (p >= P) continue;
-                                double x = x0[p * n + i] + 0.01 * (ub[p] - lb[p]) * zz[q];
-                                X[k * P + p] = x < lb[p] ? lb[p] : (x > ub[p] ? ub[p] : x);
-                            }
-                        }
+                        double r = 0.01 * (ub[p] - lb[p]);
+                        double x = x0[p * n + i] + r * (2.0 * orc_uniform(o[p % 4]) - 1.0);
+                        X[k * P + p] = x < lb[p] ? lb[p] : (x > ub[p] ? ub[p] : x);
                     }
                 }
                 lp[k] = log_lik(&m, X + k * P, y + i, n, wi, inv2s2, s);

@@ -485,3 +485,152 @@ def gc_philox_uniform_normal(seed: int, ctr, precision="fp32"):
     _check(_L.gc_philox_uniform_normal(c_uint64(seed), cp, n, 0 if dt is np.float32 else 1,
                                        ou.ctypes.data, oz.ctypes.data, ctypes.byref(ex)))
     return ou, oz
+
+
+# ------------------------------------------------------------------ server
+class Server:
+    """Continuous-batching server (gc_server_*).  Jobs carry host (numpy)
+    arrays; the server keeps them alive until the job is waited for."""
+
+    def __init__(self, device=0, hbm_budget=0, max_slots=0, chunk_iters=0, baseline=False):
+        cfg = gc_server_cfg(device, hbm_budget, max_slots, chunk_iters, 1 if baseline else 0)
+        h = c_void_p()
+        _check(_L.gc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._jobs = {}
+
+    def _common(self, model, y, mask, lb, ub, x0, x0_map):
+        keep = []
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        nx, ny, nz = _shape3(y, model)
+        keep.append(y)
+        mk = None
+        if mask is not None:
+            mk = np.ascontiguousarray(mask, dtype=np.uint8)
+            keep.append(mk)
+        P_ = model.n_params
+        lbv, ubv = _host_f64(lb, P_), _host_f64(ub, P_)
+        x0v = None if x0 is None else _host_f64(x0, P_)
+        xm = None if x0_map is None else np.ascontiguousarray(x0_map, dtype=np.float32)
+        keep += [lbv, ubv, x0v, xm]
+        job = gc_job()
+        job.model = model.handle
+        job.data = gc_volume(nx, ny, nz, y.ctypes.data)
+        job.mask = None if mk is None else mk.ctypes.data
+        job.bounds = gc_bounds(lbv.ctypes.data, ubv.ctypes.data,
+                               None if x0v is None else x0v.ctypes.data,
+                               None if xm is None else xm.ctypes.data)
+        return job, keep, (nx, ny, nz)
+
+    def submit_mcmc(self, model, y, mask, lb, ub, n_chains, n_iter, burnin, thin, *, sigma,
+                    step=None, seed=0, x0=None, x0_map=None, x0_mode="midpoint", weights=None,
+                    precision="fp32", sampler="mh", n_walkers=50, stretch=2.0, accept=True):
+        job, keep, (nx, ny, nz) = self._common(model, y, mask, lb, ub, x0, x0_map)
+        job.kind = 1
+        job.n_chains, job.n_iter, job.burnin, job.thin = n_chains, n_iter, burnin, thin
+        h = gc_mcmc_hyper()
+        _L.gc_mcmc_defaults(ctypes.byref(h))
+        h.sigma = sigma
+        st = None if step is None else _host_f64(step, model.n_params)
+        h.step = None if st is None else st.ctypes.data
+        h.seed = int(seed)
+        h.x0_mode = {"midpoint": 0, "uniform": 1, "given": 2}[x0_mode]
+        if (x0_map is not None or x0 is not None) and x0_mode == "midpoint":
+            h.x0_mode = 2
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+        h.weights = None if w is None else w.ctypes.data
+        h.precision = {"fp32": 0, "fp64": 1}[precision]
+        h.sampler = {"mh": 0, "ensemble": 1}[sampler]
+        h.n_walkers, h.stretch = n_walkers, stretch
+        job.mcmc = h
+        C = n_walkers if sampler == "ensemble" else n_chains
+        P_ = model.n_params
+        mean = np.zeros((P_, nz, ny, nx))
+        std = np.zeros((P_, nz, ny, nx))
+        acc = np.zeros((C, nz, ny, nx), np.int32) if accept else None
+        job.out_mean, job.out_std = mean.ctypes.data, std.ctypes.data
+        job.out_accept = None if acc is None else acc.ctypes.data
+        keep += [st, w]
+        out = dict(mean=mean, std=std, accept=acc)
+        return self._submit(job, keep, out)
+
+    def submit_fit(self, model, y, mask, lb, ub, *, x0=None, x0_map=None, weights=None,
+                   optimizer="adam", lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, momentum=0.9,
+                   rho=0.9, n_iter=200, loss=2, lam=0.0, tv_params=(), tv_dim=3, tol=0.0,
+                   conv_value=0.0, conv_window=20):
+        job, keep, (nx, ny, nz) = self._common(model, y, mask, lb, ub, x0, x0_map)
+        job.kind = 0
+        h = gc_adam_hyper()
+        _L.gc_adam_defaults(ctypes.byref(h))
+        h.optimizer = OPTIMIZERS[optimizer]
+        h.lr, h.beta1, h.beta2, h.eps, h.momentum, h.rho = lr, beta1, beta2, eps, momentum, rho
+        h.n_iter, h.loss = n_iter, loss
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+        h.weights = None if w is None else w.ctypes.data
+        h.lambda_ = lam
+        h.tv_mask = sum(1 << int(p) for p in tv_params)
+        h.tv_dim = tv_dim
+        h.tol, h.conv_value, h.conv_window = tol, conv_value, conv_window
+        job.adam = h
+        maps = np.zeros((model.n_params, nz, ny, nx), np.float32)
+        rep = gc_fit_report()
+        job.out_maps = maps.ctypes.data
+        job.report = ctypes.addressof(rep)
+        keep += [w, rep]
+        out = dict(maps=maps, report=rep)
+        return self._submit(job, keep, out)
+
+    def _submit(self, job, keep, out):
+        jid = c_uint64()
+        _check(_L.gc_submit(self.handle, ctypes.byref(job), ctypes.byref(jid)))
+        self._jobs[jid.value] = (job, keep, out)
+        return jid.value
+
+    def poll(self, jid) -> str:
+        st = c_int()
+        _check(_L.gc_poll(self.handle, jid, ctypes.byref(st)))
+        return JOB_STATES[st.value]
+
+    def wait(self, jid, timeout_ms=-1):
+        """Waits for a job; returns its result dict (raises GcError if it failed)."""
+        st = c_int()
+        _check(_L.gc_wait(self.handle, jid, timeout_ms, ctypes.byref(st)))
+        _, _, out = self._jobs[jid]
+        if st.value != GC_OK:
+            raise GcError(st.value, last_error())
+        r = dict(out)
+        if "report" in r:
+            rep = r.pop("report")
+            r.update(iters_run=rep.iters_run, final_loss=rep.final_loss,
+                     stop_reason=rep.stop_reason)
+        return r
+
+    def cancel(self, jid):
+        _check(_L.gc_cancel(self.handle, jid))
+
+    def latency(self, jid) -> float:
+        s = c_double()
+        _check(_L.gc_job_latency(self.handle, jid, ctypes.byref(s)))
+        return s.value
+
+    def stats(self) -> dict:
+        st = gc_stats()
+        _check(_L.gc_server_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in gc_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _L.gc_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -233,6 +233,8 @@ int fill_mh_job(const gc_model* m, const gc_bounds* b, const gc_mcmc_hyper* h, i
         J->ubd[p] = hi;
         J->stepd[p] = st;
         J->x0cd[p] = x0;
+        J->balld[p] = 0.01 * (hi - lo);
+        J->ball[p] = (float)J->balld[p];
     }
     const double inv = 1.0 / (2.0 * h->sigma * h->sigma);
     J->inv2s2 = (float)inv;

@@ -8,6 +8,14 @@
 // word 1 -> stretch z = ((a-1) u + 1)^2 / a, word 2 -> acceptance uniform;
 // accept iff log u < (P-1) log z + logL(Y) - logL(X_k), Y = X_j + z (X_k - X_j),
 // proposals outside the box rejected.
+//
+// Stretch moves multiply walker differences by up to a per accepted move, so
+// a last-bit difference in a walker grows exponentially along the chain.  The
+// walker-state arithmetic is therefore written as separate IEEE operations
+// (floating-point contraction off) and the start is exactly computable, which
+// keeps the FP64 instantiation bit-identical to a plain FP64 evaluation of
+// the same steps; only the log-likelihoods carry last-bit differences, and
+// those matter only for acceptance decisions within rounding of a tie.
 #include "gc_internal.hpp"
 
 namespace gc {
@@ -46,13 +54,19 @@ __device__ __forceinline__ int first_keep_e(int t0, int burnin, int thin) {
 
 }  // namespace
 
-// Walker start: x0 (midpoint / given / map) plus a small Gaussian ball of
-// 1 % of the box width (Box-Muller on counter (v, k | 1 << 16, 0, b)),
-// clamped to the box; x0_mode 1 = uniform in the box as for MH chains.
-// Lanes are (voxel, walker) with lane = k n + v, like MH chains.
+template <typename R> __device__ __forceinline__ R ballE(const MhJob& J, int p) {
+    if constexpr (sizeof(R) == 8) return J.balld[p]; else return J.ball[p];
+}
+
+// Walker start: x0 (midpoint / given / map) plus a uniform offset in
+// [-r, r], r = 1 % of the box width (word p % 4 of counter
+// (v, k | 1 << 16, 0, p / 4): x = x0 + r (2u - 1)), clamped to the box;
+// x0_mode 1 = uniform in the box as for MH chains.  Lanes are (voxel,
+// walker) with lane = k n + v, like MH chains.
 template <int KIND, typename R>
 __global__ __launch_bounds__(kBlock) void ens_init_kernel(const MhJob* __restrict__ jobs,
                                                          const BlkMap* __restrict__ map) {
+#pragma clang fp contract(off)
     using Mdl = typename ModelOf<KIND, R>::T;
     constexpr int P = Mdl::P;
     const BlkMap bm = map[blockIdx.x];
@@ -68,28 +82,18 @@ __global__ __launch_bounds__(kBlock) void ens_init_kernel(const MhJob* __restric
         U4 o = philox4x32_10(U4{(uint32_t)v, (uint32_t)k | (1u << 16), 0u, (uint32_t)b}, J.k0,
                              J.k1);
         const uint32_t w[4] = {o.x, o.y, o.z, o.w};
-        if (J.x0_mode == 1) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int p = 4 * b + i;
-                if (p < P) th[p] = lbE<R>(J, p) + (ubE<R>(J, p) - lbE<R>(J, p)) * uniform01<R>(w[i]);
-            }
-        } else {
-#pragma unroll
-            for (int pr = 0; pr < 2; ++pr) {
-                const R r = Math<R>::sqrt(Math<R>::m2ln(uniform01<R>(w[2 * pr])));
-                const R u2 = uniform01<R>(w[2 * pr + 1]);
-                const R zz[2] = {r * Math<R>::cos2pi(u2), r * Math<R>::sin2pi(u2)};
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int p = 4 * b + 2 * pr + q;
-                    if (p < P) {
-                        const R c = J.x0map ? (R)J.x0map[(int64_t)p * n + v] : x0E<R>(J, p);
-                        const R lo = lbE<R>(J, p), hi = ubE<R>(J, p);
-                        R x = c + (R)0.01 * (hi - lo) * zz[q];
-                        th[p] = x < lo ? lo : (x > hi ? hi : x);
-                    }
-                }
+        for (int i = 0; i < 4; ++i) {
+            const int p = 4 * b + i;
+            if (p >= P) continue;
+            const R u = uniform01<R>(w[i]);
+            const R lo = lbE<R>(J, p), hi = ubE<R>(J, p);
+            if (J.x0_mode == 1) {
+                th[p] = lo + (hi - lo) * u;
+            } else {
+                const R c = J.x0map ? (R)J.x0map[(int64_t)p * n + v] : x0E<R>(J, p);
+                const R x = c + ballE<R>(J, p) * ((R)2 * u - (R)1);
+                th[p] = x < lo ? lo : (x > hi ? hi : x);
             }
         }
     }
@@ -115,6 +119,7 @@ __global__ __launch_bounds__(kBlock) void ens_init_kernel(const MhJob* __restric
 template <int KIND, typename R>
 __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restrict__ jobs,
                                                           const BlkMap* __restrict__ map) {
+#pragma clang fp contract(off)
     using Mdl = typename ModelOf<KIND, R>::T;
     constexpr int P = Mdl::P;
     extern __shared__ unsigned char smem[];

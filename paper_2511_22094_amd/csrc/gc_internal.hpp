@@ -35,6 +35,8 @@ struct MhJob {
     double inv2s2d;
     float stretch;           // ensemble scale a
     double stretchd;
+    float ball[kMaxP];       // ensemble start: half-width of the box around x0
+    double balld[kMaxP];
     // chain state, [.][C*n] with lane = c*n + v
     void* th;                // [P][C n] Real
     void* ll;                // [C n] Real
