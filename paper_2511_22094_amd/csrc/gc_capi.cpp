@@ -63,15 +63,73 @@ DeviceScope::~DeviceScope() {
 }
 
 Scratch::~Scratch() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    for (void* p : ptrs) {
+        if (arena) arena->free(p);
+        else (void)hipFreeAsync(p, s);
+    }
 }
 
 hipError_t Scratch::alloc(void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMallocAsync(p, bytes, s);
+    hipError_t e = arena ? arena->alloc(p, bytes) : hipMallocAsync(p, bytes, s);
     if (e == hipSuccess) ptrs.push_back(*p);
     return e;
+}
+
+hipError_t DevArena::alloc(void** p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    bytes = (bytes + 255) / 256 * 256;
+    for (size_t ci = 0;; ++ci) {
+        if (ci == chunks.size()) {
+            Chunk c;
+            c.size = std::max(bytes, chunk_bytes);
+            hipError_t e = hipMalloc((void**)&c.base, c.size);
+            if (e != hipSuccess) return e;
+            c.free_[0] = c.size;
+            chunks.push_back(std::move(c));
+        }
+        Chunk& c = chunks[ci];
+        for (auto it = c.free_.begin(); it != c.free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, len = it->second;
+            c.free_.erase(it);
+            if (len > bytes) c.free_[off + bytes] = len - bytes;
+            *p = c.base + off;
+            used[c.base + off] = {ci, bytes};
+            in_use += bytes;
+            return hipSuccess;
+        }
+    }
+}
+
+void DevArena::free(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = used.find((char*)p);
+    if (it == used.end()) return;
+    Chunk& c = chunks[it->second.first];
+    size_t off = (size_t)((char*)p - c.base), len = it->second.second;
+    used.erase(it);
+    in_use -= len;
+    // coalesce with the free neighbours inside the chunk
+    auto nx = c.free_.lower_bound(off);
+    if (nx != c.free_.end() && nx->first == off + len) {
+        len += nx->second;
+        nx = c.free_.erase(nx);
+    }
+    if (nx != c.free_.begin()) {
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == off) {
+            pv->second += len;
+            return;
+        }
+    }
+    c.free_[off] = len;
+}
+
+DevArena::~DevArena() {
+    for (auto& c : chunks) (void)hipFree(c.base);
 }
 
 int stage_in(Scratch& sc, const void* p, size_t bytes, int mem_kind, const void** dptr) {

@@ -66,11 +66,33 @@ struct DeviceScope {
     ~DeviceScope();
 };
 
-// Stream-ordered scratch allocations released at scope exit.
+// Device memory owned by the host: chunks from hipMalloc, sub-allocated
+// first-fit.  A block is returned only when the host knows the GPU has
+// finished with it (after observing an event), so no stream-ordering
+// assumption is involved; the server draws all its memory from one arena.
+struct DevArena {
+    std::mutex mu;
+    struct Chunk {
+        char* base = nullptr;
+        size_t size = 0;
+        std::map<size_t, size_t> free_;   // offset -> length
+    };
+    std::vector<Chunk> chunks;
+    std::map<char*, std::pair<size_t, size_t>> used;   // ptr -> (chunk, length)
+    size_t chunk_bytes = (size_t)256 << 20;
+    size_t in_use = 0;
+    hipError_t alloc(void** p, size_t bytes);
+    void free(void* p);
+    ~DevArena();
+};
+
+// Scratch allocations released at scope exit: stream-ordered on `s`
+// (synchronous entry points, one stream), or from an arena (server).
 struct Scratch {
     hipStream_t s = nullptr;
+    DevArena* arena = nullptr;
     std::vector<void*> ptrs;
-    explicit Scratch(hipStream_t st) : s(st) {}
+    explicit Scratch(hipStream_t st, DevArena* a = nullptr) : s(st), arena(a) {}
     ~Scratch();
     hipError_t alloc(void** p, size_t bytes);
     template <typename T> hipError_t alloc_n(T** p, size_t n) {

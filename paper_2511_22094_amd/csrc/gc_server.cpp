@@ -67,6 +67,7 @@ struct Job {
     std::vector<double> lb, ub, x0, step;   // owned copies of descriptor arrays
     int state = GC_JOB_QUEUED;
     int status = GC_OK;
+    int fail_status = GC_OK;   // set when a shared launch failed for this job
     std::string err;
     bool cancel = false;
     double t_submit = 0, t_done = 0;
@@ -99,7 +100,8 @@ struct Job {
     hipEvent_t ready = nullptr, done = nullptr;
     void* pin_out = nullptr;   // pinned result staging
     void* pin_aux = nullptr;   // pinned descriptor staging of the finalisation
-    char* dout = nullptr;      // device result staging (fits)
+    char* dout = nullptr;      // device result staging (arena)
+    void* dj = nullptr;        // device descriptors of the finalisation (arena)
     int stage = 0;             // per-iteration fits: 1 = stop flag copied, 2 = maps copied
     size_t out_bytes = 0;
     int iters_run = 0, stop_reason = 0;
@@ -125,6 +127,7 @@ struct gc_server {
     size_t used = 0;
     hipStream_t prep = nullptr, compute = nullptr, copy = nullptr;
     gc::PinnedPool pinned;
+    gc::DevArena arena;              // all device memory of resident jobs and rounds
     // statistics
     uint64_t n_sub = 0, n_done = 0, n_fail = 0, n_cancel = 0;
     double voxel_iters = 0.0, busy = 0.0, busy_since = -1.0;
@@ -165,7 +168,7 @@ int64_t count_mask_host(const uint8_t* mask, int64_t G) {
 // Stage, compact and initialise one admitted job on the prep stream.
 static int prepare_job(gc_server* S, Job* J) {
     const gc_model* m = J->spec.model;
-    J->mem.reset(new Scratch(S->prep));
+    J->mem.reset(new Scratch(S->prep, &S->arena));
     Scratch& sc = *J->mem;
     int rc;
     if ((rc = model_acq(m, S->cfg.device, &J->acq))) return rc;
@@ -291,8 +294,10 @@ struct Group {
 };
 
 // Enqueue one round of shared launches on the compute stream.
-static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void*& rec_host) {
+static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void*& rec_host,
+                        void*& rec_dev) {
     rec_host = nullptr;
+    rec_dev = nullptr;
     const int chunk = S->cfg.chunk_iters > 0 ? S->cfg.chunk_iters : 500;
     std::vector<Group> groups;
     auto find = [&](int kernel, int kind, int maxm, bool fp64, int walkers) -> Group& {
@@ -391,12 +396,16 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
     char* host = (char*)S->pinned.get(bytes);
     GC_REQUIRE(host != nullptr, GC_E_NOMEM, "pinned staging of %zu bytes failed", bytes);
     char* dev = nullptr;
-    hipError_t e = hipMallocAsync((void**)&dev, bytes, S->compute);
+    hipError_t e = S->arena.alloc((void**)&dev, bytes);
     if (e != hipSuccess) {
         S->pinned.put(host);
         set_error("descriptor allocation failed");
         return GC_E_NOMEM;
     }
+    // both staging buffers belong to the round record from here on: they are
+    // released when the host has seen the round's event complete
+    rec_host = host;
+    rec_dev = dev;
     for (auto& u : ups) {
         if (!u.g->mh.empty()) std::memcpy(host + u.od, u.g->mh.data(), u.g->mh.size() * sizeof(MhJob));
         else std::memcpy(host + u.od, u.g->fit.data(), u.g->fit.size() * sizeof(FitJob));
@@ -432,10 +441,6 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
             }
         }
     }
-    GC_TRY_HIP(hipFreeAsync(dev, S->compute));
-    // the pinned staging buffer returns to the pool when this round's event
-    // has completed (the copy above has then executed)
-    rec_host = host;
     return GC_OK;
 }
 
@@ -454,13 +459,15 @@ static int finalize_job(gc_server* S, Job* J, hipEvent_t after) {
         const bool acc = J->spec.out_accept != nullptr;
         J->out_bytes = (size_t)G * P * 16 + (acc ? (size_t)G * C * 4 : 0);
         char* dout = nullptr;
-        GC_TRY_HIP(hipMallocAsync((void**)&dout, J->out_bytes, c));
+        GC_TRY_HIP(S->arena.alloc((void**)&dout, J->out_bytes));
+        J->dout = dout;
         if (n > 0) {
             MhJob q = J->mh;
             const int64_t vb = (n + kBlock - 1) / kBlock;
             MhJob* dj = nullptr;
             BlkMap* vm = nullptr;
-            GC_TRY_HIP(hipMallocAsync((void**)&dj, sizeof(MhJob) + (size_t)vb * sizeof(BlkMap), c));
+            GC_TRY_HIP(S->arena.alloc((void**)&dj, sizeof(MhJob) + (size_t)vb * sizeof(BlkMap)));
+            J->dj = dj;
             vm = (BlkMap*)((char*)dj + sizeof(MhJob));
             char* pin = (char*)S->pinned.get(sizeof(MhJob) + (size_t)vb * sizeof(BlkMap));
             GC_REQUIRE(pin, GC_E_NOMEM, "pinned staging failed");
@@ -469,7 +476,6 @@ static int finalize_job(gc_server* S, Job* J, hipEvent_t after) {
             for (int64_t b = 0; b < vb; ++b) hm[b] = BlkMap{0, 0, b * kBlock};
             GC_TRY_HIP(hipMemcpyAsync(dj, pin, sizeof(MhJob) + (size_t)vb * sizeof(BlkMap), hipMemcpyHostToDevice, c));
             GC_TRY_HIP(mh_finalize(J->fp64, dj, vm, (int)vb, J->mean_c, J->std_c, c));
-            GC_TRY_HIP(hipFreeAsync(dj, c));
             J->pin_aux = pin;
         }
         GC_TRY_HIP(scatter_rows_f64(J->mean_c, P, n, J->pk.g2c, G, (double*)dout, c));
@@ -480,11 +486,10 @@ static int finalize_job(gc_server* S, Job* J, hipEvent_t after) {
         J->pin_out = S->pinned.get(J->out_bytes);
         GC_REQUIRE(J->pin_out, GC_E_NOMEM, "pinned staging failed");
         GC_TRY_HIP(hipMemcpyAsync(J->pin_out, dout, J->out_bytes, hipMemcpyDeviceToHost, c));
-        GC_TRY_HIP(hipFreeAsync(dout, c));
     } else {
         J->out_bytes = (size_t)G * P * 4 + 3 * sizeof(double) + 2 * sizeof(int);
         char* dout = nullptr;
-        GC_TRY_HIP(hipMallocAsync((void**)&dout, J->out_bytes, c));
+        GC_TRY_HIP(S->arena.alloc((void**)&dout, J->out_bytes));
         double* dl = (double*)(dout + (size_t)G * P * 4);
         if (n > 0) {
             const float* ufin = J->u0;
@@ -561,16 +566,16 @@ static void complete_job(gc_server* S, Job* J, int status) {
             }
         }
     }
-    if (J->dout) (void)hipFreeAsync(J->dout, S->copy);
+    // every piece of GPU work on this job has completed (its rounds drained,
+    // its result copies observed), so its memory returns to the arena now
+    S->arena.free(J->dout);
+    S->arena.free(J->dj);
     J->dout = nullptr;
+    J->dj = nullptr;
     S->pinned.put(J->pin_out);
     S->pinned.put(J->pin_aux);
     J->pin_out = J->pin_aux = nullptr;
-    // device memory of the job: freed in stream order after its last use
-    if (J->mem) {
-        J->mem->s = S->copy;
-        J->mem.reset();
-    }
+    J->mem.reset();
     if (J->ready) (void)hipEventDestroy(J->ready);
     if (J->done) (void)hipEventDestroy(J->done);
     J->ready = J->done = nullptr;
@@ -595,7 +600,8 @@ static void complete_job(gc_server* S, Job* J, int status) {
 
 struct RoundRec {
     hipEvent_t ev = nullptr;
-    void* host = nullptr;
+    void* host = nullptr;      // pinned descriptor staging
+    void* dev = nullptr;       // device descriptors (arena)
     std::vector<Job*> ended;   // jobs whose last work is in this round
 };
 
@@ -641,6 +647,7 @@ static void scheduler(gc_server* S) {
             int rc = prepare_job(S, J);
             if (rc != GC_OK) {
                 J->err = gc_last_error();
+                (void)hipStreamSynchronize(S->prep);   // nothing of it may still run
                 complete_job(S, J, rc);
             } else if (J->n == 0 || J->t_total == 0) {
                 J->last_round = round - 1;
@@ -656,19 +663,28 @@ static void scheduler(gc_server* S) {
         }
         if (!active.empty()) {
             RoundRec rec;
-            int rc = launch_round(S, round, active, rec.host);
+            int rc = launch_round(S, round, active, rec.host, rec.dev);
             if (rc != GC_OK) {
-                for (Job* J : active) complete_job(S, J, rc);
+                // work of earlier rounds may still be running on these jobs:
+                // they leave (failed) only once those rounds have drained
+                const std::string msg = gc_last_error();
+                for (Job* J : active) {
+                    J->cancel = true;
+                    J->fail_status = rc;
+                    J->err = msg;
+                }
             } else {
                 for (Job* J : active)
                     if (J->t_next >= J->t_total) rec.ended.push_back(J);
-                (void)hipEventCreateWithFlags(&rec.ev, hipEventDisableTiming);
-                (void)hipEventRecord(rec.ev, S->compute);
-                inflight.push_back(std::move(rec));
-                ++round;
             }
+            // the record owns the staging buffers and marks the end of every
+            // launch enqueued so far (also after a partial failure)
+            (void)hipEventCreateWithFlags(&rec.ev, hipEventDisableTiming);
+            (void)hipEventRecord(rec.ev, S->compute);
+            inflight.push_back(std::move(rec));
+            ++round;
         }
-        // cancelled resident jobs leave once their rounds have drained
+        // cancelled (or failed) resident jobs leave once their rounds have drained
         {
             std::vector<Job*> gone;
             {
@@ -677,7 +693,7 @@ static void scheduler(gc_server* S) {
                     if (J->cancel && !J->finishing && J->last_round < round - (int)inflight.size())
                         gone.push_back(J);
             }
-            for (Job* J : gone) complete_job(S, J, GC_E_CANCELLED);
+            for (Job* J : gone) complete_job(S, J, J->fail_status != GC_OK ? J->fail_status : GC_E_CANCELLED);
         }
         // ----------------------------------------------- retire finished rounds
         while (!inflight.empty()) {
@@ -687,6 +703,7 @@ static void scheduler(gc_server* S) {
             hipError_t q = must_wait ? hipEventSynchronize(r.ev) : hipEventQuery(r.ev);
             if (q == hipErrorNotReady) break;
             S->pinned.put(r.host);
+            S->arena.free(r.dev);
             for (Job* J : r.ended)
                 if (!J->cancel && finalize_job(S, J, r.ev) != GC_OK) complete_job(S, J, GC_E_DEVICE);
             (void)hipEventDestroy(r.ev);

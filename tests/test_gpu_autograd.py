@@ -1,0 +1,63 @@
+"""torch.autograd through the hand-written adjoints: gradients of a torch
+loss built on the HIP forward model and TV term against the FP64 oracle's
+analytic gradient and against central finite differences of the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import G, say
+from paper_2511_22094_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("model", ["monoexp_t2s", "gre3", "dwi2", "linear3"])
+def test_autograd_loss_gradient(orc, model):
+    import torch
+    from paper_2511_22094_amd.autograd import forward_model
+    g = G()
+    acq = (synth.dwi_acq(np.random.default_rng(1), dirs_per_shell=12) if model == "dwi2"
+           else synth.default_acq(model))
+    m = g.Model.from_acq(model, acq)
+    n = 700
+    rng = np.random.default_rng(2)
+    lb, ub = synth.bounds(model)
+    th = rng.uniform(lb + 0.1 * (ub - lb), ub - 0.1 * (ub - lb), (n, len(lb))).T
+    y = orc.forward(model, acq, synth.draw_truth(model, rng, n)) + 0.01 * rng.standard_normal(
+        (m.n_meas_eff, n))
+    y32 = y.astype(np.float32)
+    t = torch.tensor(th, dtype=torch.float32, device="cuda", requires_grad=True)
+    yt = torch.tensor(y32, device="cuda")
+    s = forward_model(t, m)
+    loss = ((yt - s) ** 2).sum() / (n * m.n_meas_eff)
+    loss.backward()
+    gt = t.grad.double().cpu().numpy()
+    th64 = t.detach().double().cpu().numpy()
+    _, gr = orc.loss_grad(model, acq, th64, y32, p=2, scale=1.0 / (n * m.n_meas_eff))
+    err = np.abs(gt - gr) / (np.abs(gr).max(axis=1, keepdims=True) + 1e-30)
+    say(model, "autograd vs oracle analytic, max rel", err.max())
+    assert err.max() < 1e-4
+    # central finite differences of the oracle's loss on a few voxels
+    for v in range(3):
+        for p in range(len(lb)):
+            h = 1e-6 * max(1.0, abs(th64[p, v]))
+            tp, tm = th64[:, v:v + 1].copy(), th64[:, v:v + 1].copy()
+            tp[p] += h
+            tm[p] -= h
+            lp = orc.loss_grad(model, acq, tp, y32[:, v:v + 1], scale=1.0 / (n * m.n_meas_eff))[0]
+            lm = orc.loss_grad(model, acq, tm, y32[:, v:v + 1], scale=1.0 / (n * m.n_meas_eff))[0]
+            fd = (lp - lm)[0] / (2 * h)
+            assert abs(fd - gt[p, v]) <= 1e-3 * (np.abs(gr[p]).max() + 1e-30)
+
+
+def test_autograd_tv(orc):
+    import torch
+    from paper_2511_22094_amd.autograd import total_variation
+    rng = np.random.default_rng(5)
+    mask = (rng.uniform(size=(4, 5, 6)) < 0.9).astype(np.uint8)
+    u = torch.tensor(rng.uniform(size=mask.shape), dtype=torch.float32, device="cuda",
+                     requires_grad=True)
+    R = total_variation(u, torch.from_numpy(mask).cuda(), 3)
+    (3.0 * R).backward()
+    Rr, dRr = orc.tv(mask, u.detach().double().cpu().numpy(), 3, 3.0)
+    assert R.item() == pytest.approx(Rr, rel=1e-6)
+    assert np.array_equal(u.grad.cpu().numpy(), dRr.astype(np.float32))
