@@ -801,7 +801,7 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
             tm.flush();
         } else {
             GC_TRY_HIP(mh_init(model->kind, fp64, djob, dmap, (int)nblk, s));
-            const int maxm = mh_pick_maxm(model->kind, model->M);
+            const int maxm = mh_pick_variant(model->kind, model->M, model->uniform ? 1 : 0);
             LaunchTimer tm("mh_chunk", s);
             for (int c = 0; c < nck; ++c) {
                 tm.begin();

@@ -172,11 +172,23 @@ template <> struct AcqView<double> {
 template <typename R> struct UseRecur { static constexpr bool value = false; };
 template <> struct UseRecur<float> { static constexpr bool value = true; };
 
-// A measurement loop bound: compile-time MAXM > 0 fully unrolls (measured
-// data can then live in registers); MAXM == 0 is a runtime loop.
+// Compile-time evaluation choices of a kernel instantiation:
+//   MAXM  > 0: measurement loop fully unrolled up to MAXM (data can sit in
+//              registers); 0: runtime loop.
+//   EXACT = 1: the acquisition has exactly MAXM measurements (no guards).
+//   RECUR = 1: echo recurrence on, 2: off, 0: decided at run time from the
+//              acquisition (equally spaced echoes).
+enum { kRecurRuntime = 0, kRecurOn = 1, kRecurOff = 2 };
+
+template <typename R, int RECUR> __device__ __forceinline__ bool recur_on(const AcqDev& a) {
+    if constexpr (!UseRecur<R>::value || RECUR == kRecurOff) return false;
+    else if constexpr (RECUR == kRecurOn) return true;
+    else return a.uniform != 0;
+}
+
 #define GC_FOR_MEAS(m, MAXM, M)                                                 \
     _Pragma("unroll") for (int m = 0; m < ((MAXM) > 0 ? (MAXM) : (M)); ++m)    \
-        if ((MAXM) == 0 || m < (M))
+        if ((MAXM) == 0 || EXACT || m < (M))
 
 // --------------------------------------------------------------------------
 // Forward models.  Each provides
@@ -198,11 +210,11 @@ template <typename R, int KIND> struct MonoExp {
         if (KIND == MONOEXP_T2S) return -Math<R>::rcp(th[1]);
         return -th[1] * (R)1e-3;
     }
-    template <int MAXM, class Y>
+    template <int MAXM, int EXACT = 0, int RECUR = kRecurRuntime, class Y>
     static __device__ __forceinline__ R sse(const R* th, const Y& y, const AcqDev& a) {
         R k = rate(th);
         R acc0 = 0, acc1 = 0;
-        if (UseRecur<R>::value && a.uniform) {
+        if (recur_on<R, RECUR>(a)) {
             R e = th[0] * Math<R>::exp(k * AcqView<R>::te0(a));
             R q = Math<R>::exp(k * AcqView<R>::dte(a));
             GC_FOR_MEAS(m, MAXM, a.M) {
@@ -218,7 +230,7 @@ template <typename R, int KIND> struct MonoExp {
         }
         return acc0 + acc1;
     }
-    template <int MAXM, class D>
+    template <int MAXM, int EXACT = 0, int RECUR = kRecurRuntime, class D>
     static __device__ __forceinline__ void grad(const R* th, D& d, const AcqDev& a, R* g) {
         R k = rate(th);
         R gs = 0, gk = 0;   // gk accumulates sum d * s * TE
@@ -249,7 +261,7 @@ template <typename R> struct Linear3 {
     static __device__ __forceinline__ R rk(int k) {
         return k == 0 ? (R)(-1.0 / 10.0) : (k == 1 ? (R)(-1.0 / 30.0) : (R)(-1.0 / 80.0));
     }
-    template <int MAXM, class Y>
+    template <int MAXM, int EXACT = 0, int RECUR = kRecurRuntime, class Y>
     static __device__ __forceinline__ R sse(const R* th, const Y& y, const AcqDev& a) {
         R acc = 0;
         GC_FOR_MEAS(m, MAXM, a.M) {
@@ -261,7 +273,7 @@ template <typename R> struct Linear3 {
         }
         return acc;
     }
-    template <int MAXM, class D>
+    template <int MAXM, int EXACT = 0, int RECUR = kRecurRuntime, class D>
     static __device__ __forceinline__ void grad(const R* th, D& d, const AcqDev& a, R* g) {
         g[0] = g[1] = g[2] = 0;
         GC_FOR_MEAS(m, MAXM, a.M) {
@@ -306,12 +318,12 @@ template <typename R> struct Gre3 {
         ci = mag * Math<R>::sin2pi(rev);
     }
 
-    template <int MAXM, class Y>
+    template <int MAXM, int EXACT = 0, int RECUR = kRecurRuntime, class Y>
     static __device__ __forceinline__ R sse(const R* th, const Y& y, const AcqDev& a) {
         R kr[3], kp[3];
         rates(th, kr, kp);
         R accr = 0, acci = 0;
-        if (UseRecur<R>::value && a.uniform) {
+        if (recur_on<R, RECUR>(a)) {
             R te0 = AcqView<R>::te0(a), dte = AcqView<R>::dte(a);
             R zr[3], zi[3], qr[3], qi[3];
 #pragma unroll
@@ -356,12 +368,12 @@ template <typename R> struct Gre3 {
         return accr + acci;
     }
 
-    template <int MAXM, class D>
+    template <int MAXM, int EXACT = 0, int RECUR = kRecurRuntime, class D>
     static __device__ __forceinline__ void grad(const R* th, D& d, const AcqDev& a, R* g) {
         R kr[3], kp[3];
         rates(th, kr, kp);
         R gA[3] = {0, 0, 0}, gT[3] = {0, 0, 0}, gF[3] = {0, 0, 0};
-        const bool rec = UseRecur<R>::value && a.uniform;
+        const bool rec = recur_on<R, RECUR>(a);
         R ur[3], ui[3], qr[3], qi[3];
         if (rec) {
             R te0 = AcqView<R>::te0(a), dte = AcqView<R>::dte(a);
@@ -444,7 +456,7 @@ template <typename R> struct Dwi2 {
         n[6] = -st * sp;  // dn/dphi (z component 0)
         n[7] = st * cp;
     }
-    template <int MAXM, class Y>
+    template <int MAXM, int EXACT = 0, int RECUR = kRecurRuntime, class Y>
     static __device__ __forceinline__ R sse(const R* th, const Y& y, const AcqDev& a) {
         R n[8];
         dir(th, n);
@@ -460,7 +472,7 @@ template <typename R> struct Dwi2 {
         }
         return acc;
     }
-    template <int MAXM, class D>
+    template <int MAXM, int EXACT = 0, int RECUR = kRecurRuntime, class D>
     static __device__ __forceinline__ void grad(const R* th, D& d, const AcqDev& a, R* g) {
         R n[8];
         dir(th, n);

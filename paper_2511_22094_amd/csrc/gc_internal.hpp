@@ -97,6 +97,7 @@ hipError_t ens_chunk_walkers(int kind, bool fp64, const MhJob* jobs, const BlkMa
 hipError_t ens_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, int nblk,
                     hipStream_t s);
 int mh_pick_maxm(int kind, int M);
+int mh_pick_variant(int kind, int M, int uniform);   // code passed to mh_chunk
 
 // fits (gc_fit.hip)
 hipError_t fit_init(const FitJob* jobs, const BlkMap* map, int nblk, hipStream_t s);

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void mh_init_kernel(const MhJob* __restrict
 // --------------------------------------------------------------------------
 // A chunk of MH iterations [t0, t1) for every (voxel, chain) lane.
 // --------------------------------------------------------------------------
-template <int KIND, typename R, int MAXM>
+template <int KIND, typename R, int MAXM, int EXACT = 0, int RECUR = kRecurRuntime>
 __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restrict__ jobs,
                                                          const BlkMap* __restrict__ map) {
     using Mdl = typename ModelOf<KIND, R>::T;
@@ -153,8 +153,9 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
     if constexpr (MAXM > 0) {
 #pragma unroll
         for (int m = 0; m < MAXM; ++m) {
-            yr.r[m] = m < acq.M ? J.y[(int64_t)m * n + v] : 0.f;
-            if (CPLX) yr.i[m] = m < acq.M ? J.y[(int64_t)(acq.M + m) * n + v] : 0.f;
+            const bool in = EXACT || m < acq.M;
+            yr.r[m] = in ? J.y[(int64_t)m * n + v] : 0.f;
+            if (CPLX) yr.i[m] = in ? J.y[(int64_t)((EXACT ? MAXM : acq.M) + m) * n + v] : 0.f;
         }
     }
     const YGlob yg{J.y, n, v, acq.M};
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
 #pragma unroll
         for (int p = 0; p < P; ++p) the[p] = inb ? thp[p] : th[p];
         R sse;
-        if constexpr (MAXM > 0) sse = Mdl::template sse<MAXM>(the, yr, acq);
+        if constexpr (MAXM > 0) sse = Mdl::template sse<MAXM, EXACT, RECUR>(the, yr, acq);
         else sse = Mdl::template sse<0>(the, yg, acq);
         const R llp = nscale * sse;
         const bool a = inb && (Math<R>::ln(u) < llp - ll);
@@ -282,20 +283,40 @@ hipError_t mh_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, in
     return hipErrorInvalidValue;
 }
 
-template <int KIND, typename R, int MAXM>
+template <int KIND, typename R, int MAXM, int EXACT = 0, int RECUR = kRecurRuntime>
 static hipError_t chunk_t(const MhJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((mh_chunk_kernel<KIND, R, MAXM>), dim3(nblk), dim3(kBlock), 0, s, jobs,
-                       map);
+    hipLaunchKernelGGL((mh_chunk_kernel<KIND, R, MAXM, EXACT, RECUR>), dim3(nblk), dim3(kBlock), 0,
+                       s, jobs, map);
     return hipGetLastError();
 }
 
+// variant code = MAXM | exact << 16 | recurrence << 17 (see mh_pick_variant)
 template <int KIND, int A, int B, int C>
-static hipError_t chunk_f32(int maxm, const MhJob* jobs, const BlkMap* map, int nblk,
+static hipError_t chunk_f32(int variant, const MhJob* jobs, const BlkMap* map, int nblk,
                             hipStream_t s) {
+    constexpr bool kRec = KIND == MONOEXP_T2S || KIND == MONOEXP_R2S || KIND == GRE3;
+    constexpr int kExactRecur = kRec ? kRecurOn : kRecurOff;
+    const int maxm = variant & 0xFFFF;
+    const bool exact = (variant >> 16) & 1;
+    if (exact) {
+        if (maxm == A) return chunk_t<KIND, float, A, 1, kExactRecur>(jobs, map, nblk, s);
+        if (maxm == B) return chunk_t<KIND, float, B, 1, kExactRecur>(jobs, map, nblk, s);
+        if (maxm == C) return chunk_t<KIND, float, C, 1, kExactRecur>(jobs, map, nblk, s);
+    }
     if (maxm == A) return chunk_t<KIND, float, A>(jobs, map, nblk, s);
     if (maxm == B) return chunk_t<KIND, float, B>(jobs, map, nblk, s);
     if (maxm == C) return chunk_t<KIND, float, C>(jobs, map, nblk, s);
     return chunk_t<KIND, float, 0>(jobs, map, nblk, s);
+}
+
+// The exact, straight-line instantiation is used when the acquisition has
+// exactly MAXM measurements and -- for the exponential-decay models -- equally
+// spaced echoes (the recurrence then applies unconditionally).
+int mh_pick_variant(int kind, int M, int uniform) {
+    const int maxm = mh_pick_maxm(kind, M);
+    const bool rec_model = kind == MONOEXP_T2S || kind == MONOEXP_R2S || kind == GRE3;
+    const bool exact = maxm == M && (!rec_model || uniform);
+    return maxm | (exact ? 1 << 16 : 0);
 }
 
 hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkMap* map,

@@ -208,7 +208,7 @@ static int prepare_job(gc_server* S, Job* J) {
         GC_TRY_HIP(sc.alloc_n(&J->mean_c, (size_t)std::max<int64_t>(n, 1) * P));
         GC_TRY_HIP(sc.alloc_n(&J->std_c, (size_t)std::max<int64_t>(n, 1) * P));
         J->t_total = J->spec.n_iter;
-        J->maxm = mh_pick_maxm(m->kind, m->M);
+        J->maxm = mh_pick_variant(m->kind, m->M, m->uniform ? 1 : 0);
         if (n > 0) {
             const int64_t nb = (n * J->C + kBlock - 1) / kBlock;
             std::vector<BlkMap> mp((size_t)nb);
