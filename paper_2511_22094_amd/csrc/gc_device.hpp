@@ -461,12 +461,18 @@ template <typename R> struct Dwi2 {
         R n[8];
         dir(th, n);
         R acc = 0;
+        // the ball term depends on b only: on a shell (consecutive equal b,
+        // a uniform test) it is reused instead of recomputed -- same values
+        R bprev = (R)-1, ball = 0;
         GC_FOR_MEAS(m, MAXM, a.M) {
             R x = AcqView<R>::g(a, m, 0) * n[0] + AcqView<R>::g(a, m, 1) * n[1] +
                   AcqView<R>::g(a, m, 2) * n[2];
             R b = AcqView<R>::b(a, m);
-            R s = th[0] * Math<R>::exp(-b * th[1] * x * x) +
-                  ((R)1 - th[0]) * Math<R>::exp(-b * th[2]);
+            if (b != bprev) {
+                ball = ((R)1 - th[0]) * Math<R>::exp(-b * th[2]);
+                bprev = b;
+            }
+            R s = th[0] * Math<R>::exp(-b * th[1] * x * x) + ball;
             R r = (R)y.re(m) - s;
             acc += r * r;
         }
@@ -477,13 +483,17 @@ template <typename R> struct Dwi2 {
         R n[8];
         dir(th, n);
         R gf = 0, gda = 0, gde = 0, gn0 = 0, gn1 = 0, gn2 = 0;
+        R bprev = (R)-1, Ee = 0;   // ball term reused along a shell (see sse)
         GC_FOR_MEAS(m, MAXM, a.M) {
             R g0 = AcqView<R>::g(a, m, 0), g1 = AcqView<R>::g(a, m, 1),
               g2 = AcqView<R>::g(a, m, 2);
             R b = AcqView<R>::b(a, m);
             R x = g0 * n[0] + g1 * n[1] + g2 * n[2];
             R Ea = Math<R>::exp(-b * th[1] * x * x);
-            R Ee = Math<R>::exp(-b * th[2]);
+            if (b != bprev) {
+                Ee = Math<R>::exp(-b * th[2]);
+                bprev = b;
+            }
             R dj = d.re(m, th[0] * Ea + ((R)1 - th[0]) * Ee);
             gf += dj * (Ea - Ee);
             R t = dj * b * Ea;      // d * b * Ea
