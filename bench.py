@@ -136,6 +136,19 @@ def adam_leg(g, torch, steps, warmup):
                 achieved_gbs=gbs, final_loss=r["final_loss"], n=n)
 
 
+def copy_leg(torch, mib=256, reps=3):
+    """A plain device copy of known size (mib MiB read + mib MiB written per launch): the
+    calibration launch for the HBM byte counters."""
+    n = mib * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return dict(bytes_read=n * 4, bytes_written=n * 4, launches=reps)
+
+
 SERVE_MODELS = {
     "monoexp_t2s": 0.01,
     "gre3": 0.01,
@@ -251,6 +264,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving leg on the full 256-job trace (voxels up to 1e6)")
+    ap.add_argument("--profile-only", default=None,
+                    help="comma list of mh, adam, copy: run only these legs once each (no "
+                         "warm-up, no headline line) for hardware counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -259,6 +275,23 @@ def main():
     import torch
     from paper_2511_22094_amd import lib
     g = lib()
+    if args.profile_only:
+        legs = [x.strip() for x in args.profile_only.split(",") if x.strip()]
+        rep = {}
+        for leg in legs:
+            log(f"bench: profile leg {leg}")
+            if leg == "mh":
+                r = mh_leg(g, torch, 1, 0)
+                rep[leg] = {"launches": r["launches"], "per_launch_ms": r["per_launch_ms"]}
+            elif leg == "adam":
+                r = adam_leg(g, torch, 1, 0)
+                rep[leg] = {"per_launch_us": r["per_launch_us"], "n": r["n"]}
+            elif leg == "copy":
+                rep[leg] = copy_leg(torch)
+            else:
+                raise SystemExit(f"unknown profile leg {leg!r}")
+        print(json.dumps({"profile_only": rep}))
+        return
     log("bench: MH leg (gre3 128x128x64, 4 chains x 5000)")
     mh = mh_leg(g, torch, args.steps, args.warmup)
     log(f"bench: MH {mh['value']:.3e} voxel-iter/s, {mh['sec']:.3f} s/step, "

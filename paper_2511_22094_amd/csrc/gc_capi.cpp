@@ -621,7 +621,10 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
             float* partial = nullptr;
             double* hist = nullptr;
             int* stop = nullptr;
-            GC_TRY_HIP(sc.alloc_n(&partial, (size_t)nblk * T));
+            // the loss is reduced on every iteration only when a stopping rule or
+            // the history needs it, else once, on the last iteration
+            const bool each = stopping || history;
+            GC_TRY_HIP(sc.alloc_n(&partial, (size_t)nblk * (each ? T : 1)));
             GC_TRY_HIP(sc.alloc_n(&hist, (size_t)T));
             GC_TRY_HIP(sc.alloc_n(&stop, 2));
             GC_TRY_HIP(fill_i32(stop, 2, 0, s));
@@ -637,8 +640,8 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
                 q.u_in = (t % 2 == 1) ? u0 : u1;
                 q.u_out = (t % 2 == 1) ? u1 : u0;
                 q.nbr = nbr;
-                q.record = 1;
-                q.partial = partial + (size_t)(t - 1) * nblk;
+                q.record = (each || t == T) ? 1 : 0;
+                q.partial = partial + (each ? (size_t)(t - 1) * nblk : 0);
                 q.blk0 = 0;
                 q.stop = stop;
             }
@@ -653,8 +656,9 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
                 tm.begin();
                 GC_TRY_HIP(fit_step(model->kind, djob + (t - 1), dmap, (int)nblk, 1, s));
                 tm.end();
-                GC_TRY_HIP(fit_loss_stop(jobs[t - 1].partial, nblk, hist, t, tol,
-                                         hyper->conv_value, hyper->conv_window, stop, s));
+                if (jobs[t - 1].record)
+                    GC_TRY_HIP(fit_loss_stop(jobs[t - 1].partial, nblk, hist, t, tol,
+                                             hyper->conv_value, hyper->conv_window, stop, s));
                 if (stopping && t % poll == 0 && t < T) {
                     GC_TRY_HIP(hipMemcpyAsync(hstop, stop, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
                     GC_TRY_HIP(hipStreamSynchronize(s));
@@ -668,11 +672,16 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
                 iters = hstop[0];
                 reason = hstop[1];
             }
-            std::vector<double> hh((size_t)iters);
-            GC_TRY_HIP(hipMemcpyAsync(hh.data(), hist, iters * sizeof(double), hipMemcpyDeviceToHost, s));
-            GC_TRY_HIP(hipStreamSynchronize(s));
-            final_loss = hh[iters - 1];
-            if (history) std::memcpy(hyper->loss_history, hh.data(), iters * sizeof(double));
+            if (history) {
+                GC_TRY_HIP(hipMemcpyAsync(hyper->loss_history, hist, iters * sizeof(double),
+                                          hipMemcpyDeviceToHost, s));
+                GC_TRY_HIP(hipStreamSynchronize(s));
+                final_loss = hyper->loss_history[iters - 1];
+            } else {
+                GC_TRY_HIP(hipMemcpyAsync(&final_loss, hist + (iters - 1), sizeof(double),
+                                          hipMemcpyDeviceToHost, s));
+                GC_TRY_HIP(hipStreamSynchronize(s));
+            }
             const float* ufin = (iters % 2 == 1) ? u1 : u0;
             GC_TRY_HIP(fit_theta(P, J.lb, J.rng, ufin, n, theta_c, s));
         }

@@ -87,6 +87,7 @@ struct Job {
     // fit
     FitJob fit{};
     bool step_path = false;
+    bool loss_each = false;   // stopping rules need the loss of every iteration
     float *u0 = nullptr, *u1 = nullptr, *theta_c = nullptr, *lossv = nullptr, *partial = nullptr;
     double* hist = nullptr;
     int* stop = nullptr;
@@ -151,7 +152,9 @@ size_t footprint_of(const gc_model* m, const gc_job& j, int64_t G, int64_t n) {
         b += (size_t)n * m->P * 16 + (size_t)G * m->P * 16 + (size_t)G * C * 4;
     } else {
         b += (size_t)n * m->P * 4 * 5 + (size_t)n * 24 + (size_t)G * m->P * 4;
-        b += (size_t)((n + kBlock - 1) / kBlock) * j.adam.n_iter * 4 + (size_t)j.adam.n_iter * 8;
+        const bool each = j.adam.tol > 0 || j.adam.conv_value > 0;
+        b += (size_t)((n + kBlock - 1) / kBlock) * (each ? j.adam.n_iter : 1) * 4 +
+             (size_t)j.adam.n_iter * 8;
     }
     return b + (1 << 20);
 }
@@ -251,12 +254,13 @@ static int prepare_job(gc_server* S, Job* J) {
                                             J->spec.data.nz, h.tv_dim, nbr, S->prep));
             }
             q.nbr = nbr;
-            GC_TRY_HIP(sc.alloc_n(&J->partial, (size_t)std::max<int64_t>(J->nblk, 1) * h.n_iter));
+            J->loss_each = h.tol > 0 || h.conv_value > 0;
+            GC_TRY_HIP(sc.alloc_n(&J->partial, (size_t)std::max<int64_t>(J->nblk, 1) *
+                                                   (J->loss_each ? h.n_iter : 1)));
             GC_TRY_HIP(sc.alloc_n(&J->hist, (size_t)h.n_iter));
             GC_TRY_HIP(sc.alloc_n(&J->stop, 2));
             GC_TRY_HIP(fill_i32(J->stop, 2, 0, S->prep));
             q.stop = J->stop;
-            q.record = 1;
         } else {
             GC_TRY_HIP(sc.alloc_n(&J->lossv, (size_t)std::max<int64_t>(n, 1)));
             q.loss_v = J->lossv;
@@ -291,6 +295,7 @@ struct Group {
     std::vector<FitJob> fit;
     std::vector<BlkMap> map;
     std::vector<Job*> owners;   // fit_step: owner per descriptor (loss / stop launches)
+    std::vector<int> iter;      // fit_step: iteration of each descriptor (1-based)
 };
 
 // Enqueue one round of shared launches on the compute stream.
@@ -305,7 +310,7 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
             if (g.kernel == kernel && g.kind == kind && g.maxm == maxm && g.fp64 == fp64 &&
                 g.walkers == walkers)
                 return g;
-        groups.push_back(Group{kernel, kind, maxm, walkers, fp64, {}, {}, {}, {}});
+        groups.push_back(Group{kernel, kind, maxm, walkers, fp64, {}, {}, {}, {}, {}});
         return groups.back();
     };
     // fit_step jobs advance in sub-steps: one launch per iteration, all such jobs together
@@ -366,19 +371,23 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
             q.u = J->u0;
             q.u_in = (t % 2 == 1) ? J->u0 : J->u1;
             q.u_out = (t % 2 == 1) ? J->u1 : J->u0;
-            q.partial = J->partial + (size_t)(t - 1) * J->nblk;
+            // the loss is reduced on every iteration only under stopping rules,
+            // else once, on the last iteration (the reported final loss)
+            q.record = (J->loss_each || t == J->t_total) ? 1 : 0;
+            q.partial = J->partial + (J->loss_each ? (size_t)(t - 1) * J->nblk : 0);
             J->t_next = t;
             Group* g = nullptr;
             for (auto& x : gs)
                 if (x.kind == J->kind) g = &x;
             if (!g) {
-                gs.push_back(Group{3, J->kind, 0, 0, false, {}, {}, {}, {}});
+                gs.push_back(Group{3, J->kind, 0, 0, false, {}, {}, {}, {}, {}});
                 g = &gs.back();
             }
             const int jb = (int)g->fit.size();
             q.blk0 = (int64_t)g->map.size();
             g->fit.push_back(q);
             g->owners.push_back(J);
+            g->iter.push_back(t);
             for (int64_t v0 = 0; v0 < J->n; v0 += kBlock) g->map.push_back(BlkMap{jb, 0, v0});
         }
         if (gs.empty()) break;
@@ -432,9 +441,10 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
             const FitJob* dj = (const FitJob*)(dev + u.od);
             GC_TRY_HIP(fit_step(g.kind, dj, (const BlkMap*)(dev + u.om), nb, 1, S->compute));
             for (size_t k = 0; k < g.fit.size(); ++k) {
+                if (!g.fit[k].record) continue;
                 Job* J = g.owners[k];
                 const gc_adam_hyper& h = J->spec.adam;
-                const int t = (int)((g.fit[k].partial - J->partial) / std::max<int64_t>(J->nblk, 1)) + 1;
+                const int t = g.iter[k];
                 GC_TRY_HIP(fit_loss_stop(g.fit[k].partial, J->nblk, J->hist, t,
                                          h.tol > 0 ? h.tol : -INFINITY, h.conv_value,
                                          h.conv_window, J->stop, S->compute));
