@@ -57,6 +57,15 @@ def lib():
         L.orc_loss_grad.argtypes = [i32, i32, P, P, P, P, P, P, i64, i32, dbl, P, P]
         L.orc_tv.argtypes = [i32, i32, i32, P, P, i32, dbl, P]
         L.orc_tv.restype = dbl
+        L.orc_tv_iso.argtypes = [i32, i32, i32, P, P, i32, dbl, P]
+        L.orc_tv_iso.restype = dbl
+        L.orc_tv_graph.argtypes = [i64, P, P, P, dbl, P]
+        L.orc_tv_graph.restype = dbl
+        L.orc_prior.argtypes = [i64, P, dbl, dbl, P, P, dbl, P]
+        L.orc_prior.restype = dbl
+        L.orc_askadam_reg.argtypes = ([i32, i32, P, P, P, i32, i32, i32, P, P, P, P, P, P,
+                                       i32, dbl, dbl, dbl, dbl, dbl, dbl, i32, i32, dbl, u32,
+                                       i32, P, dbl, dbl, i32, P, P, P, P, i32])
         L.orc_askadam.argtypes = ([i32, i32, P, P, P, i32, i32, i32, P, P, P, P, P, P,
                                    i32, dbl, dbl, dbl, dbl, dbl, dbl, i32, i32, dbl, u32,
                                    i32, dbl, dbl, i32, P, P, P, P, i32])
@@ -214,6 +223,45 @@ def tv(mask: np.ndarray, u: np.ndarray, dim: int = 3, scale: float = 1.0):
     return R, dR
 
 
+def tv_iso(mask: np.ndarray, u: np.ndarray, dim: int = 3, scale: float = 1.0):
+    """Isotropic grid TV: returns (R, dR) for a full grid u[nz, ny, nx]."""
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    u = _f64(u)
+    nz, ny, nx = mask.shape
+    dR = np.zeros_like(u)
+    R = lib().orc_tv_iso(nx, ny, nz, _p(mask), _p(u), dim, scale, _p(dR))
+    return R, dR
+
+
+def tv_graph(rowptr, col, u, scale: float = 1.0):
+    """Graph TV over CSR adjacency (rowptr [n+1], col): returns (R, dR [n])."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    u = _f64(u)
+    dR = np.zeros_like(u)
+    R = lib().orc_tv_graph(u.size, _p(rowptr), _p(col), _p(u), scale, _p(dR))
+    return R, dR
+
+
+def prior(u, lb, ub, mu, sigma, scale: float = 1.0):
+    """Prior regulariser of one map over n voxels: returns (R, dR/du [n])."""
+    u = _f64(u)
+    mu = _f64(np.broadcast_to(mu, u.shape))
+    sigma = _f64(np.broadcast_to(sigma, u.shape))
+    dR = np.zeros_like(u)
+    R = lib().orc_prior(u.size, _p(u), float(lb), float(ub), _p(mu), _p(sigma), scale, _p(dR))
+    return R, dR
+
+
+class _Reg(ctypes.Structure):
+    _fields_ = [("tv_kind", ctypes.c_int), ("graph_n", ctypes.c_int64),
+                ("graph_rowptr", ctypes.c_void_p), ("graph_col", ctypes.c_void_p),
+                ("prior_lambda", ctypes.c_double), ("prior_mask", ctypes.c_uint32),
+                ("prior_mu", ctypes.c_void_p), ("prior_sigma", ctypes.c_void_p)]
+
+
+TV_KINDS = {"aniso": 0, "iso": 1, "graph": 2}
+
 # ---------------------------------------------------------------- askadam
 OPTIMIZERS = {"adam": 0, "sgdm": 1, "rmsprop": 2}
 
@@ -221,8 +269,12 @@ OPTIMIZERS = {"adam": 0, "sgdm": 1, "rmsprop": 2}
 def askadam(model: str, acq, mask, y_grid, lb, ub, *, x0=None, w=None, optimizer="adam",
             lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, momentum=0.9, rho=0.9,
             n_iter=200, loss=2, lam=0.0, tv_mask=0, tv_dim=3, tol=0.0, conv_value=0.0,
-            conv_window=20, n_threads=0):
-    """Returns dict(maps [P,nz,ny,nx], loss [iters_run], iters_run, stop_reason)."""
+            conv_window=20, n_threads=0, tv_kind="aniso", graph=None, prior_lam=0.0,
+            prior_mask=0, prior_mu=None, prior_sigma=None):
+    """Returns dict(maps [P,nz,ny,nx], loss [iters_run], iters_run, stop_reason).
+
+    tv_kind: "aniso" | "iso" (grid) | "graph" with graph = (rowptr, col) over
+    the masked voxels in grid order; prior_mu / prior_sigma: [P, nz, ny, nx]."""
     a = Acq.of(acq)
     mask = np.ascontiguousarray(mask, dtype=np.uint8)
     nz, ny, nx = mask.shape
@@ -236,11 +288,25 @@ def askadam(model: str, acq, mask, y_grid, lb, ub, *, x0=None, w=None, optimizer
     hist = np.zeros(max(n_iter, 1))
     it = ctypes.c_int()
     reason = ctypes.c_int()
-    rc = lib().orc_askadam(MODEL_IDS[model], *a.args(), nx, ny, nz, _p(mask), _p(y), _p(w),
-                           _p(lb), _p(ub), _p(x0), OPTIMIZERS[optimizer], lr, beta1, beta2,
-                           eps, momentum, rho, n_iter, loss, lam, tv_mask, tv_dim, tol,
-                           conv_value, conv_window, _p(maps), _p(hist), ctypes.byref(it),
-                           ctypes.byref(reason), n_threads)
+    reg = _Reg()
+    reg.tv_kind = TV_KINDS[tv_kind]
+    keep = []
+    if graph is not None:
+        rp = np.ascontiguousarray(graph[0], dtype=np.int64)
+        cl = np.ascontiguousarray(graph[1], dtype=np.int32)
+        keep += [rp, cl]
+        reg.graph_n, reg.graph_rowptr, reg.graph_col = rp.size - 1, rp.ctypes.data, cl.ctypes.data
+    if prior_lam:
+        mu = _f64(np.broadcast_to(prior_mu, (P, nz, ny, nx)))
+        sg = _f64(np.broadcast_to(prior_sigma, (P, nz, ny, nx)))
+        keep += [mu, sg]
+        reg.prior_lambda, reg.prior_mask = prior_lam, prior_mask
+        reg.prior_mu, reg.prior_sigma = mu.ctypes.data, sg.ctypes.data
+    rc = lib().orc_askadam_reg(MODEL_IDS[model], *a.args(), nx, ny, nz, _p(mask), _p(y), _p(w),
+                               _p(lb), _p(ub), _p(x0), OPTIMIZERS[optimizer], lr, beta1, beta2,
+                               eps, momentum, rho, n_iter, loss, lam, tv_mask, tv_dim,
+                               ctypes.byref(reg), tol, conv_value, conv_window, _p(maps),
+                               _p(hist), ctypes.byref(it), ctypes.byref(reason), n_threads)
     assert rc == 0, rc
     return dict(maps=maps, loss=hist[: it.value], iters_run=it.value, stop_reason=reason.value)
 

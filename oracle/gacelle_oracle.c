@@ -409,6 +409,92 @@ double orc_tv(int nx, int ny, int nz, const uint8_t *mask, const double *u, int 
 }
 
 /* ------------------------------------------------------------------------
+ * Isotropic reading of the grid TV of Eq. 5: per masked voxel a, the
+ * Euclidean norm of its forward differences (only those whose neighbour is
+ * in the mask, along x, y and, in 3D, z):
+ *   R(u) = sum_a G_a,  G_a = sqrt(sum_d (u_{a+e_d} - u_a)^2).
+ * Subgradient: dG_a/du_{a+e_d} = D_d / G_a, dG_a/du_a = -sum_d D_d / G_a,
+ * and 0 when G_a = 0.  dR is accumulated (+=) with weight `scale`.
+ * ------------------------------------------------------------------------ */
+double orc_tv_iso(int nx, int ny, int nz, const uint8_t *mask, const double *u, int dim,
+                  double scale, double *dR) {
+    double R = 0.0;
+    int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t a = z * sz + y * sy + x * sx;
+                if (!mask[a]) continue;
+                int64_t nb[3] = {a + sx, a + sy, a + sz};
+                int ok[3] = {x + 1 < nx, y + 1 < ny, dim == 3 && z + 1 < nz};
+                double D[3] = {0.0, 0.0, 0.0};
+                double ss = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    ok[d] = ok[d] && mask[nb[d]];
+                    if (!ok[d]) continue;
+                    D[d] = u[nb[d]] - u[a];
+                    ss += D[d] * D[d];
+                }
+                double Ga = sqrt(ss);
+                R += Ga;
+                if (dR && Ga > 0.0)
+                    for (int d = 0; d < 3; ++d) {
+                        if (!ok[d]) continue;
+                        dR[nb[d]] += scale * D[d] / Ga;
+                        dR[a] -= scale * D[d] / Ga;
+                    }
+            }
+    return R;
+}
+
+/* ------------------------------------------------------------------------
+ * Graph (surface-mesh) TV, the vertex form of Eq. 5 in the surface-fitting
+ * demonstration (§2.6.1): for each vertex i the sum over its mesh neighbours
+ * N(i) of |u_i - u_j|, summed over all vertices,
+ *   R(u) = sum_i sum_{j in N(i)} |u_i - u_j|
+ * (a symmetric adjacency counts every edge from both ends).  The adjacency is
+ * CSR over the n vertices: neighbours of i are col[rowptr[i] .. rowptr[i+1]).
+ * Subgradient with sign(0) = 0, accumulated (+=) with weight `scale`.
+ * ------------------------------------------------------------------------ */
+double orc_tv_graph(int64_t n, const int64_t *rowptr, const int32_t *col, const double *u,
+                    double scale, double *dR) {
+    double R = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int64_t j = col[k];
+            double diff = u[i] - u[j];
+            R += fabs(diff);
+            if (dR) {
+                double sg = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
+                dR[i] += scale * sg;
+                dR[j] -= scale * sg;
+            }
+        }
+    return R;
+}
+
+/* ------------------------------------------------------------------------
+ * Prior regulariser of Eq. 6: R = sum_v |(theta_v - mu_v) / sigma_v| for one
+ * parameter map, theta = lb + (ub - lb) u.  The subgradient with respect to
+ * u is sign(theta - mu) (ub - lb) / sigma (sign(0) = 0), accumulated (+=)
+ * with weight `scale`.  Arrays are over n voxels.
+ * ------------------------------------------------------------------------ */
+double orc_prior(int64_t n, const double *u, double lb, double ub, const double *mu,
+                 const double *sigma, double scale, double *dR) {
+    double R = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+        double th = lb + (ub - lb) * u[v];
+        double r = (th - mu[v]) / sigma[v];
+        R += fabs(r);
+        if (dR) {
+            double sg = r > 0 ? 1.0 : (r < 0 ? -1.0 : 0.0);
+            dR[v] += scale * sg * (ub - lb) / sigma[v];
+        }
+    }
+    return R;
+}
+
+/* ------------------------------------------------------------------------
  * askadam: whole-volume gradient fit (paper §2.2.1, Eq. 2 / Eq. 4).
  *
  * Readings: bounds are enforced by optimising normalised coordinates
@@ -453,6 +539,31 @@ static double ols_slope(const double *L, int W, int t_last) {
     return sxy / sxx;
 }
 
+/* Regularisers of the loss (§2.4): TV (Eq. 5) on the maps of tv_mask in one of
+ * three forms, and the prior (Eq. 6) on the maps of prior_mask.  Both are
+ * divided by the number N of masked voxels, like the data term:
+ *   L = D + lambda / N sum_{q in TV} R_TV(u_q)
+ *         + prior_lambda / N sum_{q in prior} sum_v |(theta_qv - mu_qv) / sigma_qv|. */
+typedef struct {
+    int tv_kind;                 /* 0 anisotropic grid, 1 isotropic grid, 2 graph */
+    int64_t graph_n;             /* graph: vertices = masked voxels in grid order */
+    const int64_t *graph_rowptr; /* [graph_n + 1] */
+    const int32_t *graph_col;    /* compact vertex indices */
+    double prior_lambda;
+    uint32_t prior_mask;
+    const double *prior_mu;      /* [P][grid] */
+    const double *prior_sigma;   /* [P][grid] */
+} orc_reg;
+
+int orc_askadam_reg(int model, int M, const double *te, const double *bval, const double *bvec,
+                    int nx, int ny, int nz, const uint8_t *mask, const float *y,
+                    const float *w, const double *lb, const double *ub, const double *x0,
+                    int optimizer, double lr, double beta1, double beta2, double eps,
+                    double momentum, double rho, int n_iter, int loss_p, double lambda,
+                    uint32_t tv_mask, int tv_dim, const orc_reg *reg, double tol,
+                    double conv_value, int conv_window, double *out_maps, double *loss_hist,
+                    int *iters_run, int *stop_reason, int n_threads);
+
 int orc_askadam(int model, int M, const double *te, const double *bval, const double *bvec,
                 int nx, int ny, int nz, const uint8_t *mask, const float *y /*[Meff][grid]*/,
                 const float *w /*[grid] or NULL*/, const double *lb, const double *ub,
@@ -462,6 +573,20 @@ int orc_askadam(int model, int M, const double *te, const double *bval, const do
                 uint32_t tv_mask, int tv_dim, double tol, double conv_value, int conv_window,
                 double *out_maps /*[P][grid]*/, double *loss_hist /*[n_iter]*/,
                 int *iters_run, int *stop_reason, int n_threads) {
+    return orc_askadam_reg(model, M, te, bval, bvec, nx, ny, nz, mask, y, w, lb, ub, x0,
+                           optimizer, lr, beta1, beta2, eps, momentum, rho, n_iter, loss_p,
+                           lambda, tv_mask, tv_dim, NULL, tol, conv_value, conv_window,
+                           out_maps, loss_hist, iters_run, stop_reason, n_threads);
+}
+
+int orc_askadam_reg(int model, int M, const double *te, const double *bval, const double *bvec,
+                    int nx, int ny, int nz, const uint8_t *mask, const float *y,
+                    const float *w, const double *lb, const double *ub, const double *x0,
+                    int optimizer, double lr, double beta1, double beta2, double eps,
+                    double momentum, double rho, int n_iter, int loss_p, double lambda,
+                    uint32_t tv_mask, int tv_dim, const orc_reg *reg, double tol,
+                    double conv_value, int conv_window, double *out_maps, double *loss_hist,
+                    int *iters_run, int *stop_reason, int n_threads) {
     orc_model m;
     if (make_model(&m, model, M, te, bval, bvec)) return -1;
     int P = m.P;
@@ -480,6 +605,22 @@ int orc_askadam(int model, int M, const double *te, const double *bval, const do
             double x = x0 ? x0[p * G + a] : 0.5 * (lb[p] + ub[p]);
             u[p * G + a] = mask[a] ? (x - lb[p]) / (ub[p] - lb[p]) : 0.0;
         }
+    const int tv_kind = reg ? reg->tv_kind : 0;
+    /* graph TV and the prior work on the masked voxels in grid order */
+    int64_t *c2g = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    {
+        int64_t k = 0;
+        for (int64_t a = 0; a < G; ++a)
+            if (mask[a]) c2g[k++] = a;
+    }
+    if (tv_kind == 2 && lambda != 0.0 && tv_mask && (!reg->graph_rowptr || reg->graph_n != N)) {
+        free(u); free(mm); free(vv); free(gr); free(lv); free(c2g);
+        return -3;
+    }
+    double *uc = (double *)malloc(sizeof(double) * (size_t)N);
+    double *gc = (double *)malloc(sizeof(double) * (size_t)N);
+    double *muc = (double *)malloc(sizeof(double) * (size_t)N);
+    double *sgc = (double *)malloc(sizeof(double) * (size_t)N);
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
@@ -506,12 +647,34 @@ int orc_askadam(int model, int M, const double *te, const double *bval, const do
         }
         double L = 0.0;
         for (int64_t a = 0; a < G; ++a) L += lv[a];
-        /* regulariser */
+        /* regularisers */
         if (lambda != 0.0) {
             for (int p = 0; p < P; ++p) {
                 if (!((tv_mask >> p) & 1u)) continue;
-                L += lambda / (double)N *
-                     orc_tv(nx, ny, nz, mask, u + p * G, tv_dim, lambda / (double)N, gr + p * G);
+                const double sc = lambda / (double)N;
+                if (tv_kind == 0) {
+                    L += sc * orc_tv(nx, ny, nz, mask, u + p * G, tv_dim, sc, gr + p * G);
+                } else if (tv_kind == 1) {
+                    L += sc * orc_tv_iso(nx, ny, nz, mask, u + p * G, tv_dim, sc, gr + p * G);
+                } else {
+                    for (int64_t k = 0; k < N; ++k) { uc[k] = u[p * G + c2g[k]]; gc[k] = 0.0; }
+                    L += sc * orc_tv_graph(N, reg->graph_rowptr, reg->graph_col, uc, sc, gc);
+                    for (int64_t k = 0; k < N; ++k) gr[p * G + c2g[k]] += gc[k];
+                }
+            }
+        }
+        if (reg && reg->prior_lambda != 0.0) {
+            for (int p = 0; p < P; ++p) {
+                if (!((reg->prior_mask >> p) & 1u)) continue;
+                const double sc = reg->prior_lambda / (double)N;
+                for (int64_t k = 0; k < N; ++k) {
+                    uc[k] = u[p * G + c2g[k]];
+                    muc[k] = reg->prior_mu[p * G + c2g[k]];
+                    sgc[k] = reg->prior_sigma[p * G + c2g[k]];
+                    gc[k] = 0.0;
+                }
+                L += sc * orc_prior(N, uc, lb[p], ub[p], muc, sgc, sc, gc);
+                for (int64_t k = 0; k < N; ++k) gr[p * G + c2g[k]] += gc[k];
             }
         }
         loss_hist[t - 1] = L;
@@ -549,6 +712,7 @@ int orc_askadam(int model, int M, const double *te, const double *bval, const do
         for (int64_t a = 0; a < G; ++a)
             out_maps[p * G + a] = mask[a] ? lb[p] + (ub[p] - lb[p]) * u[p * G + a] : 0.0;
     free(u); free(mm); free(vv); free(gr); free(lv);
+    free(c2g); free(uc); free(gc); free(muc); free(sgc);
     return 0;
 }
 
