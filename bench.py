@@ -48,6 +48,28 @@ BYTES_PER_ADAM_TV_VOXEL_ITER = 96 * 4 + 2 * 5 * 4 + 2 * 2 * 5 * 4 + 6 * 4   # = 
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernels, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE) of `bench.py --profile-only mh,adam,copy`
+# (summaries under profiles/); FETCH_SIZE is scaled by the factor that a
+# 256 MiB device copy in the same run gives (bytes it reads / its FETCH_SIZE),
+# WRITE_SIZE likewise.  A figure holds only for the kernel sources it was
+# taken on: when their sha256 differs, `traffic` is reported as null.
+MEASURED_TRAFFIC = {}
+
+
+def measured_traffic(key):
+    import hashlib
+    e = MEASURED_TRAFFIC.get(key)
+    if e is None:
+        return None
+    h = hashlib.sha256()
+    for f in e["sources"]:
+        with open(os.path.join(ROOT, "paper_2511_22094_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != e["sha256"]:
+        return None
+    return e["read_bytes"] + e["write_bytes"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -92,9 +114,11 @@ def mh_leg(g, torch, steps, warmup):
     units_per_launch = units / launches_per_step
     achieved = FLOP_PER_MH_STEP_GRE3 * units_per_launch / per_launch_s / 1e12
     finite = bool(torch.isfinite(mean).all().item())
+    idx = torch.from_numpy(cpu_sample()).to(dev)
+    moments = (mean.reshape(9, -1)[:, idx].cpu().numpy(), std.reshape(9, -1)[:, idx].cpu().numpy())
     return dict(units=units, sec=sec, value=units / sec, per_launch_ms=per_launch_s * 1e3,
                 launches=launches_per_step, achieved_tflops=achieved, finite=finite,
-                n=n, workload=d)
+                n=n, workload=d, moments=moments)
 
 
 def adam_leg(g, torch, steps, warmup):
@@ -119,7 +143,9 @@ def adam_leg(g, torch, steps, warmup):
         run()
     torch.cuda.synchronize()
     g.gc_timing_reset()
-    g.gc_timing_enable(True)
+    # every 10th launch: the event records of timing would otherwise add
+    # to the gaps between the 500 short per-iteration launches
+    g.gc_timing_enable(True, every=10)
     t0 = time.perf_counter()
     for _ in range(steps):
         r = run()
@@ -233,25 +259,47 @@ def serve_leg(g, torch, full=False):
     return out
 
 
-def cpu_baseline(sample_vox=6144):
-    """The FP64 oracle on a fixed voxel sample of the MH workload, all host threads."""
+def cpu_sample(sample_vox=6144):
+    """The fixed voxel sample of the MH workload that the CPU baseline runs."""
+    from paper_2511_22094_amd import synth
+    d = synth.cfg1()
+    rng = np.random.default_rng(1234)
+    return np.sort(rng.choice(d.n, sample_vox, replace=False))
+
+
+def cpu_baseline(sample_vox=6144, gpu_moments=None):
+    """The FP64 oracle on a fixed voxel sample of the MH workload, all host
+    threads.  With gpu_moments = (mean, std) of the GPU run at the sampled
+    voxels ([P, sample]), also the GPU result's error against the oracle on
+    that sample (each side made its data with its own forward model)."""
     import oracle
     from paper_2511_22094_amd import synth
     d = synth.cfg1()
     kw = synth.CFG1_MCMC
-    rng = np.random.default_rng(1234)
-    idx = np.sort(rng.choice(d.n, sample_vox, replace=False))
+    idx = cpu_sample(sample_vox)
     y = (oracle.forward("gre3", d.acq, d.truth[:, idx]) + d.sigma * d.noise[:, idx]).astype(np.float32)
     threads = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
-    oracle.mh("gre3", d.acq, y, d.lb, d.ub, synth.MH_STEP["gre3"], d.sigma, 1, vidx=idx,
-              n_threads=threads, **kw)
+    ref = oracle.mh("gre3", d.acq, y, d.lb, d.ub, synth.MH_STEP["gre3"], d.sigma, 1, vidx=idx,
+                    n_threads=threads, **kw)
     sec = time.perf_counter() - t0
     units = sample_vox * kw["n_chains"] * kw["n_iter"]
-    return dict(value=units / sec, unit="voxel-iterations/s", cores=threads, kind="oracle",
-                sample=f"{sample_vox} random voxels of the 128x128x64 gre3 volume, "
-                       f"{kw['n_chains']} chains x {kw['n_iter']} iterations, "
-                       f"FP64, {sec:.1f} s")
+    out = dict(value=units / sec, unit="voxel-iterations/s", cores=threads, kind="oracle",
+               sample=f"{sample_vox} random voxels of the 128x128x64 gre3 volume, "
+                      f"{kw['n_chains']} chains x {kw['n_iter']} iterations, "
+                      f"FP64, {sec:.1f} s")
+    err = None
+    if gpu_moments is not None:
+        gm, gs = gpu_moments
+        sd = np.maximum(ref["std"], 1e-300)
+        dm = np.abs(gm - ref["mean"]) / sd
+        ds = np.abs(gs - ref["std"]) / sd
+        err = {"what": "|GPU - oracle| of the posterior mean and SD, in units of the "
+                       "oracle's posterior SD, over the sampled voxels x 9 parameters "
+                       "(FP32 chains vs FP64 chains on the same random streams)",
+               "mean_median": float(np.median(dm)), "mean_p99": float(np.quantile(dm, 0.99)),
+               "sd_median": float(np.median(ds)), "sd_p99": float(np.quantile(ds, 0.99))}
+    return out, err
 
 
 def main():
@@ -305,10 +353,10 @@ def main():
     serve = None
     if not args.no_serve:
         serve = serve_leg(g, torch, args.serve_full)
-    cpu = None
+    cpu = oracle_err = None
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        cpu = cpu_baseline()
+        cpu, oracle_err = cpu_baseline(gpu_moments=mh["moments"])
         log(f"bench: CPU {cpu['value']:.3e} voxel-iter/s on {cpu['cores']} threads")
     out = {
         "metric": "voxel-iterations/sec (MCMC MH & Adam steps) at 1 GPU",
@@ -329,9 +377,11 @@ def main():
         "roofline": {"bound": "alu", "kernel": "mh_chunk<gre3,f32,24>",
                      "achieved": mh["achieved_tflops"], "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": mh["achieved_tflops"] / PEAK_FP32_TFLOPS,
-                     "traffic": None, "flop_per_step": FLOP_PER_MH_STEP_GRE3,
+                     "traffic": measured_traffic("mh_chunk"),
+                     "flop_per_step": FLOP_PER_MH_STEP_GRE3,
                      "launch_ms": mh["per_launch_ms"]},
         "cpu_baseline": cpu,
+        "oracle_error": oracle_err,
     }
     if adam is not None:
         out["adam"] = {"value": adam["value"], "unit": "voxel-iterations/s",
@@ -341,7 +391,7 @@ def main():
                        "roofline": {"bound": "hbm", "kernel": "fit_step<dwi2>",
                                     "achieved": adam["achieved_gbs"], "peak": PEAK_HBM_GBS,
                                     "unit": "GB/s", "frac": adam["achieved_gbs"] / PEAK_HBM_GBS,
-                                    "traffic": None,
+                                    "traffic": measured_traffic("fit_step"),
                                     "bytes_per_voxel_iter": BYTES_PER_ADAM_TV_VOXEL_ITER,
                                     "launch_us": adam["per_launch_us"]}}
     if serve is not None:

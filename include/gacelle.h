@@ -134,16 +134,28 @@ int gc_count_mask(const uint8_t *mask, int64_t n_grid, int64_t *n_masked,
  *
  * Objective in normalised coordinates u = (theta - lb)/(ub - lb) in [0,1]:
  *   L(u) = 1/(N M_eff) sum_{v in mask} sum_j |w_v (y_vj - s_vj)|^p
- *        + lambda/N sum_{q in TV set} sum_{neighbour pairs (a,b) in mask} |u_q(b) - u_q(a)|
+ *        + lambda/N sum_{q in TV set} R_TV(u_q)
+ *        + prior_lambda/N sum_{q in prior set} sum_v |(theta_qv - mu_qv) / sigma_qv|
  * N = masked voxels; p = 2 (squared) or 1 (real and imaginary parts count
- * separately); TV pairs are forward neighbours along x, y (and z if
- * tv_dim = 3).  After every update u is clamped to [0,1].  Iteration t
+ * separately).  R_TV (Eq. 5) takes one of three forms (tv_kind):
+ *   GC_TV_ANISO  sum over forward neighbour pairs (a,b) in the mask of
+ *                |u(b) - u(a)|, along x, y (and z if tv_dim = 3);
+ *   GC_TV_ISO    sum over masked voxels a of sqrt(sum_d (u(a+e_d) - u(a))^2),
+ *                the same forward differences (subgradient 0 where the norm
+ *                is 0);
+ *   GC_TV_GRAPH  sum over vertices i of sum_{j in N(i)} |u_i - u_j| (the
+ *                surface-mesh form of §2.6.1), N(i) from a CSR adjacency over
+ *                the masked voxels in grid order (vertex k = k-th masked
+ *                voxel); the adjacency must be symmetric, so each edge counts
+ *                from both ends.
+ * The prior term is Eq. 6.  After every update u is clamped to [0,1].  Iteration t
  * evaluates L and its (sub)gradient at u_{t-1}, updates to u_t, then stops
  * if L_t < tol (reason 1), if |least-squares slope of the last conv_window
  * losses| < conv_value once t >= conv_window (reason 2), or at t = n_iter
  * (reason 0).  out_maps receives the last iterate theta(u_t).
  * ------------------------------------------------------------------------ */
 enum { GC_OPT_ADAM = 0, GC_OPT_SGDM = 1, GC_OPT_RMSPROP = 2 };
+enum { GC_TV_ANISO = 0, GC_TV_ISO = 1, GC_TV_GRAPH = 2 };
 
 typedef struct {
     int optimizer;         /* GC_OPT_* */
@@ -162,6 +174,18 @@ typedef struct {
     double conv_value;     /* stop when |slope| < conv_value (0 = off) */
     int conv_window;       /* window length (> 1; default 20) */
     double *loss_history;  /* host [n_iter] per-iteration loss, or NULL */
+    int tv_kind;           /* GC_TV_* (default GC_TV_ANISO) */
+    int64_t graph_n;       /* GC_TV_GRAPH: vertices, = number of masked voxels */
+    int64_t graph_nnz;     /* GC_TV_GRAPH: adjacency entries */
+    const int64_t *graph_rowptr; /* [graph_n + 1] CSR offsets: rowptr[0] = 0,
+                                    non-decreasing, rowptr[graph_n] = graph_nnz
+                                    (exec memory; checked on the device) */
+    const int32_t *graph_col;    /* [graph_nnz] neighbour vertices in [0, graph_n)
+                                    (exec memory; checked on the device) */
+    double prior_lambda;   /* Eq. 6 weight (0 = off) */
+    uint32_t prior_mask;   /* bit p set: prior on parameter p */
+    const float *prior_mu;    /* [P][nz][ny][nx] prior means (exec memory) */
+    const float *prior_sigma; /* [P][nz][ny][nx] prior SDs > 0 (exec memory) */
 } gc_adam_hyper;
 
 typedef struct {
@@ -248,6 +272,19 @@ int gc_loss_vjp(const gc_model *m, const float *theta, const float *y, const flo
  * (0 outside the mask). */
 int gc_tv(int nx, int ny, int nz, const uint8_t *mask, const float *u, int tv_dim,
           double scale, double *R, float *dR, const gc_exec *exec);
+/* Isotropic form of the same (GC_TV_ISO above): *R = sum over masked voxels
+ * of the Euclidean norm of their in-mask forward differences; dR as gc_tv. */
+int gc_tv_iso(int nx, int ny, int nz, const uint8_t *mask, const float *u, int tv_dim,
+              double scale, double *R, float *dR, const gc_exec *exec);
+/* Graph TV (GC_TV_GRAPH above, §2.6.1) of one vertex map u[n]:
+ * *R = sum_i sum_{j in N(i)} |u_i - u_j| (FP64 sum, host pointer);
+ * dR[n] (exec memory, may be NULL) = scale * subgradient, which for the
+ * required symmetric adjacency is 2 sum_{j in N(i)} sign(u_i - u_j).
+ * rowptr [n+1] (int64) and col [nnz] (int32) in exec memory; both are
+ * checked on the device first (GC_E_INVAL unless rowptr[0] = 0, rowptr is
+ * non-decreasing, rowptr[n] = nnz and every col entry is in [0, n)). */
+int gc_tv_graph(int64_t n, const int64_t *rowptr, const int32_t *col, int64_t nnz,
+                const float *u, double scale, double *R, float *dR, const gc_exec *exec);
 
 /* ------------------------------------------------------------------------
  * Counter-based random stream (for bit-exact tests against the oracle).
@@ -262,10 +299,14 @@ int gc_philox_uniform_normal(uint64_t seed, const uint32_t *ctr, int64_t n, int 
                              void *out_u, void *out_z, const gc_exec *exec);
 
 /* ------------------------------------------------------------------------
- * Kernel timing (profiling aid).  While enabled, every launch of a hot
- * kernel family is bracketed by HIP events recorded on the stream it runs
- * on; totals accumulate per family: "mh_chunk", "ens_chunk", "fit_fused",
- * "fit_step".  Costs two event records per launch; off by default.
+ * Kernel timing (profiling aid).  While enabled, launches of a hot kernel
+ * family are bracketed by HIP events recorded on the stream they run on;
+ * totals accumulate per family: "mh_chunk", "ens_chunk", "fit_fused",
+ * "fit_step".  on = 0 disables (the default); on = k > 0 times every k-th
+ * launch of a family within one call (k = 1: every launch), which bounds
+ * the cost of the two event records per timed launch for families launched
+ * once per iteration.  The count returned by gc_timing_get is that of the
+ * timed launches.
  * ------------------------------------------------------------------------ */
 int gc_timing_enable(int on);
 /* Total event time (ms) and launch count of a family since the last reset. */

@@ -16,7 +16,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgacelle.so")
+# GACELLE_LIB names another build of the same library (e.g. one compiled
+# with different tuning); the default is the in-tree build.
+LIB_PATH = os.environ.get("GACELLE_LIB") or os.path.join(_HERE, "libgacelle.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -74,7 +76,13 @@ class gc_adam_hyper(ctypes.Structure):
                 ("rho", c_double), ("n_iter", c_int), ("loss", c_int), ("weights", c_void_p),
                 ("lambda_", c_double), ("tv_mask", c_uint32), ("tv_dim", c_int),
                 ("tol", c_double), ("conv_value", c_double), ("conv_window", c_int),
-                ("loss_history", c_void_p)]
+                ("loss_history", c_void_p), ("tv_kind", c_int), ("graph_n", c_int64),
+                ("graph_nnz", c_int64), ("graph_rowptr", c_void_p), ("graph_col", c_void_p),
+                ("prior_lambda", c_double), ("prior_mask", c_uint32), ("prior_mu", c_void_p),
+                ("prior_sigma", c_void_p)]
+
+
+TV_KINDS = {"aniso": 0, "iso": 1, "graph": 2}
 
 
 class gc_fit_report(ctypes.Structure):
@@ -131,6 +139,10 @@ _sig = {
     "gc_loss_vjp": ([P, P, P, P, c_int64, c_int, c_double, P, P, ctypes.POINTER(gc_exec)], c_int),
     "gc_tv": ([c_int, c_int, c_int, P, P, c_int, c_double, ctypes.POINTER(c_double), P,
                ctypes.POINTER(gc_exec)], c_int),
+    "gc_tv_iso": ([c_int, c_int, c_int, P, P, c_int, c_double, ctypes.POINTER(c_double), P,
+                   ctypes.POINTER(gc_exec)], c_int),
+    "gc_tv_graph": ([c_int64, P, P, c_int64, P, c_double, ctypes.POINTER(c_double), P,
+                     ctypes.POINTER(gc_exec)], c_int),
     "gc_philox": ([c_uint64, P, c_int64, P, ctypes.POINTER(gc_exec)], c_int),
     "gc_philox_uniform_normal": ([c_uint64, P, c_int64, c_int, P, P, ctypes.POINTER(gc_exec)], c_int),
     "gc_timing_enable": ([c_int], c_int),
@@ -154,8 +166,9 @@ for _name, (_args, _res) in _sig.items():
     _f.restype = _res
 
 
-def gc_timing_enable(on: bool = True):
-    _L.gc_timing_enable(1 if on else 0)
+def gc_timing_enable(on=True, every: int = 1):
+    """on: enable / disable; every = k times every k-th launch of a family within a call."""
+    _L.gc_timing_enable(max(int(every), 1) if on else 0)
 
 
 def gc_timing_reset():
@@ -209,7 +222,7 @@ class _Args:
                 raise TypeError("torch tensors must live on the GPU (use numpy for host data)")
             want = {np.float32: torch.float32, np.float64: torch.float64,
                     np.uint8: torch.uint8, np.int32: torch.int32,
-                    np.uint32: torch.int32}[dtype]
+                    np.uint32: torch.int32, np.int64: torch.int64}[dtype]
             if a.dtype != want and not (dtype is np.uint32 and a.dtype == torch.int32):
                 raise TypeError(f"expected {want}, got {a.dtype}")
             if not a.is_contiguous():
@@ -274,10 +287,12 @@ class Model:
         return cls(name, getattr(acq, "te", None), getattr(acq, "bval", None),
                    getattr(acq, "bvec", None))
 
-    def __del__(self):
+    # the destroy entry point is bound at definition time: at interpreter
+    # shutdown the module globals may already have been cleared
+    def __del__(self, _destroy=_L.gc_model_destroy):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            _L.gc_model_destroy(h)
+            _destroy(h)
             self.handle = None
 
 
@@ -329,8 +344,13 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
                    optimizer="adam", lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, momentum=0.9,
                    rho=0.9, n_iter=200, loss=2, lam=0.0, tv_params: Sequence[int] = (),
                    tv_dim=3, tol=0.0, conv_value=0.0, conv_window=20, loss_history=False,
-                   out=None):
-    """Returns dict(maps [P, nz, ny, nx] float32, iters_run, final_loss, stop_reason[, loss])."""
+                   out=None, tv_kind="aniso", graph=None, prior_lam=0.0,
+                   prior_params: Sequence[int] = (), prior_mu=None, prior_sigma=None):
+    """Returns dict(maps [P, nz, ny, nx] float32, iters_run, final_loss, stop_reason[, loss]).
+
+    tv_kind "aniso" | "iso" | "graph" (graph = (rowptr [n+1] int64, col int32) over the
+    masked voxels in grid order); prior_mu / prior_sigma [P, nz, ny, nx] for the prior
+    term on prior_params."""
     a = _Args()
     nx, ny, nz = _shape3(y, model)
     vol = gc_volume(nx, ny, nz, a.ptr(y, np.float32))
@@ -346,6 +366,8 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
     h.tv_mask = sum(1 << int(p) for p in tv_params)
     h.tv_dim = tv_dim
     h.tol, h.conv_value, h.conv_window = tol, conv_value, conv_window
+    _set_regularisers(h, a, model, tv_kind, graph, prior_lam, prior_params, prior_mu,
+                      prior_sigma)
     hist = np.zeros(max(n_iter, 1)) if loss_history else None
     h.loss_history = None if hist is None else hist.ctypes.data
     maps = out if out is not None else _empty_like_kind(a, (model.n_params, nz, ny, nx),
@@ -448,8 +470,8 @@ def gc_loss_vjp(model: Model, theta, y, w=None, p=2, scale=1.0):
     return loss, g
 
 
-def gc_tv(u, mask=None, tv_dim=3, scale=1.0, grad=True):
-    """u [nz, ny, nx] float32 -> (R float, dR like u or None)."""
+def gc_tv(u, mask=None, tv_dim=3, scale=1.0, grad=True, kind="aniso"):
+    """u [nz, ny, nx] float32 -> (R float, dR like u or None); kind "aniso" | "iso"."""
     a = _Args()
     nz, ny, nx = (int(s) for s in u.shape)
     up = a.ptr(u, np.float32)
@@ -458,8 +480,55 @@ def gc_tv(u, mask=None, tv_dim=3, scale=1.0, grad=True):
     dp = a.out(dR, np.float32)
     R = c_double()
     ex = a.exec()
-    _check(_L.gc_tv(nx, ny, nz, mp, up, tv_dim, scale, ctypes.byref(R), dp, ctypes.byref(ex)))
+    fn = {"aniso": _L.gc_tv, "iso": _L.gc_tv_iso}[kind]
+    _check(fn(nx, ny, nz, mp, up, tv_dim, scale, ctypes.byref(R), dp, ctypes.byref(ex)))
     return R.value, dR
+
+
+def gc_tv_iso(u, mask=None, tv_dim=3, scale=1.0, grad=True):
+    return gc_tv(u, mask, tv_dim, scale, grad, kind="iso")
+
+
+def gc_tv_graph(rowptr, col, u, scale=1.0, grad=True):
+    """Graph TV of a vertex map u [n] over CSR (rowptr [n+1] int64, col int32)
+    -> (R float, dR like u or None)."""
+    a = _Args()
+    n = int(u.shape[0])
+    rp = a.ptr(rowptr, np.int64)
+    cp = a.ptr(col, np.int32)
+    up = a.ptr(u, np.float32)
+    dR = _empty_like_kind(a, (n,), np.float32, u) if grad else None
+    dp = a.out(dR, np.float32)
+    R = c_double()
+    ex = a.exec()
+    _check(_L.gc_tv_graph(n, rp, cp, int(col.shape[0]), up, scale, ctypes.byref(R), dp,
+                          ctypes.byref(ex)))
+    return R.value, dR
+
+
+def _set_regularisers(h, a, model, tv_kind, graph, prior_lam, prior_params, prior_mu,
+                      prior_sigma, keep=None):
+    """Fills the TV-form, graph and prior fields of a gc_adam_hyper."""
+    h.tv_kind = TV_KINDS[tv_kind]
+    if graph is not None:
+        rowptr, col = graph
+        h.graph_n = int(rowptr.shape[0]) - 1
+        h.graph_nnz = int(col.shape[0])
+        h.graph_rowptr = a.ptr(rowptr, np.int64) if a is not None else _host(rowptr, np.int64, keep)
+        h.graph_col = a.ptr(col, np.int32) if a is not None else _host(col, np.int32, keep)
+    if prior_lam:
+        h.prior_lambda = prior_lam
+        h.prior_mask = sum(1 << int(p) for p in prior_params)
+        h.prior_mu = a.ptr(prior_mu, np.float32) if a is not None else \
+            _host(prior_mu, np.float32, keep)
+        h.prior_sigma = a.ptr(prior_sigma, np.float32) if a is not None else \
+            _host(prior_sigma, np.float32, keep)
+
+
+def _host(x, dt, keep):
+    arr = np.ascontiguousarray(x, dtype=dt)
+    keep.append(arr)
+    return arr.ctypes.data
 
 
 def gc_philox(seed: int, ctr):
@@ -557,7 +626,8 @@ class Server:
     def submit_fit(self, model, y, mask, lb, ub, *, x0=None, x0_map=None, weights=None,
                    optimizer="adam", lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, momentum=0.9,
                    rho=0.9, n_iter=200, loss=2, lam=0.0, tv_params=(), tv_dim=3, tol=0.0,
-                   conv_value=0.0, conv_window=20):
+                   conv_value=0.0, conv_window=20, tv_kind="aniso", graph=None,
+                   prior_lam=0.0, prior_params=(), prior_mu=None, prior_sigma=None):
         job, keep, (nx, ny, nz) = self._common(model, y, mask, lb, ub, x0, x0_map)
         job.kind = 0
         h = gc_adam_hyper()
@@ -571,6 +641,8 @@ class Server:
         h.tv_mask = sum(1 << int(p) for p in tv_params)
         h.tv_dim = tv_dim
         h.tol, h.conv_value, h.conv_window = tol, conv_value, conv_window
+        _set_regularisers(h, None, model, tv_kind, graph, prior_lam, prior_params, prior_mu,
+                          prior_sigma, keep)
         job.adam = h
         maps = np.zeros((model.n_params, nz, ny, nx), np.float32)
         rep = gc_fit_report()

@@ -21,7 +21,7 @@ SOURCES = ["gc_pack.hip", "gc_mh.hip", "gc_ens.hip", "gc_fit.hip", "gc_capi.cpp"
 ARCH = os.environ.get("GACELLE_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
-          "-Wno-unused-function", "-Wno-pass-failed", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wno-unused-function", "-Wno-pass-failed", "-Wno-cuda-compat", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 

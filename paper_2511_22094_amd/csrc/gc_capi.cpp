@@ -266,6 +266,73 @@ int pack_problem(Scratch& sc, const gc_model* m, const gc_volume* data, const ui
     return GC_OK;
 }
 
+int pack_prior(Scratch& sc, const gc_model* m, const gc_adam_hyper* h, const Packed& pk,
+               int mem_kind, float** mu, float** sigma) {
+    *mu = nullptr;
+    *sigma = nullptr;
+    if (!(h->prior_lambda > 0) || h->prior_mask == 0) return GC_OK;
+    const hipStream_t s = sc.s;
+    const int64_t G = pk.G, n = pk.n;
+    const size_t bytes = (size_t)G * m->P * sizeof(float);
+    const void *dmu, *dsg;
+    int rc;
+    if ((rc = stage_in(sc, h->prior_mu, bytes, mem_kind, &dmu))) return rc;
+    if ((rc = stage_in(sc, h->prior_sigma, bytes, mem_kind, &dsg))) return rc;
+    int* flag = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&flag, 2));
+    GC_TRY_HIP(fill_i32(flag, 2, 0, s));
+    const size_t np = (size_t)std::max<int64_t>(n, 1) * m->P;
+    GC_TRY_HIP(sc.alloc_n(mu, np));
+    GC_TRY_HIP(sc.alloc_n(sigma, np));
+    GC_TRY_HIP(gather_rows((const float*)dmu, m->P, G, pk.c2g, n, *mu, flag, s));
+    GC_TRY_HIP(gather_rows((const float*)dsg, m->P, G, pk.c2g, n, *sigma, flag, s));
+    GC_TRY_HIP(check_positive(*sigma, n * m->P, flag + 1, s));
+    int hf[2] = {0, 0};
+    GC_TRY_HIP(hipMemcpyAsync(hf, flag, sizeof(hf), hipMemcpyDeviceToHost, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    GC_REQUIRE(hf[0] == 0, GC_E_NONFINITE, "non-finite prior mean or SD inside the mask");
+    GC_REQUIRE(hf[1] == 0, GC_E_INVAL, "prior SDs must be > 0 inside the mask");
+    return GC_OK;
+}
+
+int validate_graph(Scratch& sc, int64_t n, int64_t nnz, const int64_t* rowptr,
+                   const int32_t* col, hipStream_t s) {
+    int* flag = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&flag, 1));
+    GC_TRY_HIP(fill_i32(flag, 1, 0, s));
+    GC_TRY_HIP(check_graph(n, nnz, rowptr, col, flag, s));
+    int h = 0;
+    GC_TRY_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    GC_REQUIRE(h == 0, GC_E_INVAL,
+               "graph adjacency: rowptr must start at 0, not decrease and end at nnz; "
+               "neighbour indices must lie in [0, n)");
+    return GC_OK;
+}
+
+int pack_graph(Scratch& sc, const gc_adam_hyper* h, int64_t n, int mem_kind,
+               const int64_t** rowptr, const int32_t** col) {
+    *rowptr = nullptr;
+    *col = nullptr;
+    if (!(h->lambda > 0) || h->tv_mask == 0 || h->tv_kind != GC_TV_GRAPH) return GC_OK;
+    GC_REQUIRE(h->graph_n == n, GC_E_INVAL,
+               "graph_n (%lld) must equal the number of masked voxels (%lld)",
+               (long long)h->graph_n, (long long)n);
+    if (n == 0) return GC_OK;
+    const void *drp, *dcol = nullptr;
+    int rc;
+    if ((rc = stage_in(sc, h->graph_rowptr, (size_t)(n + 1) * 8, mem_kind, &drp))) return rc;
+    if (h->graph_nnz > 0 &&
+        (rc = stage_in(sc, h->graph_col, (size_t)h->graph_nnz * 4, mem_kind, &dcol)))
+        return rc;
+    if ((rc = validate_graph(sc, n, h->graph_nnz, (const int64_t*)drp, (const int32_t*)dcol,
+                             sc.s)))
+        return rc;
+    *rowptr = (const int64_t*)drp;
+    *col = (const int32_t*)dcol;
+    return GC_OK;
+}
+
 int fill_mh_job(const gc_model* m, const gc_bounds* b, const gc_mcmc_hyper* h, int n_chains,
                 int n_iter, int burnin, int thin, const AcqDev& acq, MhJob* J) {
     std::memset((void*)J, 0, sizeof(MhJob));
@@ -311,6 +378,8 @@ int fill_fit_job(const gc_model* m, const gc_bounds* b, const gc_adam_hyper* h, 
     J->loss_p = h->loss;
     J->optimizer = h->optimizer;
     J->tv_mask = h->lambda > 0 ? h->tv_mask : 0u;
+    J->tv_kind = h->tv_kind;
+    J->prior_mask = h->prior_lambda > 0 ? h->prior_mask : 0u;
     for (int p = 0; p < m->P; ++p) {
         const double lo = b->lb[p], hi = b->ub[p];
         J->lb[p] = (float)lo;
@@ -332,12 +401,13 @@ int fill_fit_job(const gc_model* m, const gc_bounds* b, const gc_adam_hyper* h, 
     const double N = (double)(n > 0 ? n : 1);
     J->scale_data = (float)(1.0 / (N * m->Meff));
     J->scale_tv = (float)(h->lambda / N);
+    J->scale_prior = (float)(h->prior_lambda / N);
     J->active = 1;
     J->acq = acq;
     return GC_OK;
 }
 
-static int validate_adam(const gc_model* m, const gc_adam_hyper* h) {
+int validate_adam(const gc_model* m, const gc_adam_hyper* h) {
     GC_REQUIRE(h, GC_E_INVAL, "hyper missing");
     GC_REQUIRE(h->n_iter >= 1, GC_E_INVAL, "n_iter must be >= 1");
     GC_REQUIRE(h->loss == 1 || h->loss == 2, GC_E_INVAL, "loss must be 1 or 2");
@@ -350,6 +420,18 @@ static int validate_adam(const gc_model* m, const gc_adam_hyper* h) {
     GC_REQUIRE(h->lambda >= 0 && std::isfinite(h->lambda), GC_E_INVAL, "lambda must be >= 0");
     GC_REQUIRE(h->tv_dim == 2 || h->tv_dim == 3, GC_E_INVAL, "tv_dim must be 2 or 3");
     GC_REQUIRE((h->tv_mask >> m->P) == 0, GC_E_INVAL, "tv_mask names a parameter >= P");
+    GC_REQUIRE(h->tv_kind >= GC_TV_ANISO && h->tv_kind <= GC_TV_GRAPH, GC_E_INVAL,
+               "unknown tv_kind");
+    if (h->lambda > 0 && h->tv_mask && h->tv_kind == GC_TV_GRAPH) {
+        GC_REQUIRE(h->graph_rowptr && h->graph_nnz >= 0 && (h->graph_col || h->graph_nnz == 0),
+                   GC_E_INVAL, "graph TV needs graph_rowptr, graph_col and graph_nnz >= 0");
+        GC_REQUIRE(h->graph_n < INT32_MAX, GC_E_INVAL, "graph too large (n >= 2^31)");
+    }
+    GC_REQUIRE(h->prior_lambda >= 0 && std::isfinite(h->prior_lambda), GC_E_INVAL,
+               "prior_lambda must be >= 0");
+    GC_REQUIRE((h->prior_mask >> m->P) == 0, GC_E_INVAL, "prior_mask names a parameter >= P");
+    GC_REQUIRE(!(h->prior_lambda > 0 && h->prior_mask) || (h->prior_mu && h->prior_sigma),
+               GC_E_INVAL, "the prior needs prior_mu and prior_sigma");
     GC_REQUIRE(!(h->conv_value > 0) || h->conv_window > 1, GC_E_INVAL,
                "conv_window must be > 1");
     return GC_OK;
@@ -536,14 +618,20 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
     const int P = model->P;
     const int64_t n = pk.n, G = pk.G;
     const int T = hyper->n_iter;
-    if (bounds->x0_map) {
-        // start values must lie inside the bounds (checked on the host copy)
-    }
     FitJob J;
     if ((rc = fill_fit_job(model, bounds, hyper, n, acq, &J))) return rc;
     J.y = pk.y;
     J.w = pk.w;
     J.x0map = pk.x0;
+    float *pmu = nullptr, *psg = nullptr;
+    if ((rc = pack_prior(sc, model, hyper, pk, ds.mem_kind, &pmu, &psg))) return rc;
+    J.mu = pmu;
+    J.sigma = psg;
+    const int64_t* grp = nullptr;
+    const int32_t* gcol = nullptr;
+    if ((rc = pack_graph(sc, hyper, n, ds.mem_kind, &grp, &gcol))) return rc;
+    J.g_rowptr = grp;
+    J.g_col = gcol;
     float *u0 = nullptr, *u1 = nullptr, *m = nullptr, *v = nullptr;
     const size_t np = (size_t)std::max<int64_t>(n, 1) * P;
     GC_TRY_HIP(sc.alloc_n(&u0, np));
@@ -613,7 +701,7 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
         } else {
             // step path: one launch per iteration, double-buffered iterate
             int32_t* nbr = nullptr;
-            if (tv) {
+            if (tv && hyper->tv_kind != GC_TV_GRAPH) {
                 GC_TRY_HIP(sc.alloc_n(&nbr, (size_t)n * 6));
                 GC_TRY_HIP(build_neighbours(pk.c2g, pk.g2c, n, data->nx, data->ny, data->nz,
                                             hyper->tv_dim, nbr, s));
@@ -950,8 +1038,8 @@ int gc_loss_vjp(const gc_model* m, const float* theta, const float* y, const flo
     GC_GUARD_END
 }
 
-int gc_tv(int nx, int ny, int nz, const uint8_t* mask, const float* u, int tv_dim, double scale,
-          double* R, float* dR, const gc_exec* exec) {
+static int tv_entry(int kind, int nx, int ny, int nz, const uint8_t* mask, const float* u,
+                    int tv_dim, double scale, double* R, float* dR, const gc_exec* exec) {
     GC_GUARD_BEGIN
     clear_error();
     GC_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && u && R && (tv_dim == 2 || tv_dim == 3),
@@ -970,12 +1058,60 @@ int gc_tv(int nx, int ny, int nz, const uint8_t* mask, const float* u, int tv_di
     double *part = nullptr, *dsum = nullptr;
     GC_TRY_HIP(sc.alloc_n(&part, (size_t)nblk));
     GC_TRY_HIP(sc.alloc_n(&dsum, 1));
-    GC_TRY_HIP(tv_grid(nx, ny, nz, (const uint8_t*)dm, (const float*)du, tv_dim, (float)scale, part,
-                       nblk, dd, ds.stream));
+    if (kind == GC_TV_ISO)
+        GC_TRY_HIP(tv_grid_iso(nx, ny, nz, (const uint8_t*)dm, (const float*)du, tv_dim,
+                               (float)scale, part, nblk, dd, ds.stream));
+    else
+        GC_TRY_HIP(tv_grid(nx, ny, nz, (const uint8_t*)dm, (const float*)du, tv_dim, (float)scale,
+                           part, nblk, dd, ds.stream));
     GC_TRY_HIP(sum_partials_f64(part, nblk, dsum, ds.stream));
     GC_TRY_HIP(hipMemcpyAsync(R, dsum, sizeof(double), hipMemcpyDeviceToHost, ds.stream));
     if (dR && ds.mem_kind == GC_MEM_HOST)
         GC_TRY_HIP(hipMemcpyAsync(dR, dd, (size_t)G * 4, hipMemcpyDeviceToHost, ds.stream));
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_tv(int nx, int ny, int nz, const uint8_t* mask, const float* u, int tv_dim, double scale,
+          double* R, float* dR, const gc_exec* exec) {
+    return tv_entry(GC_TV_ANISO, nx, ny, nz, mask, u, tv_dim, scale, R, dR, exec);
+}
+
+int gc_tv_iso(int nx, int ny, int nz, const uint8_t* mask, const float* u, int tv_dim,
+              double scale, double* R, float* dR, const gc_exec* exec) {
+    return tv_entry(GC_TV_ISO, nx, ny, nz, mask, u, tv_dim, scale, R, dR, exec);
+}
+
+int gc_tv_graph(int64_t n, const int64_t* rowptr, const int32_t* col, int64_t nnz,
+                const float* u, double scale, double* R, float* dR, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    GC_REQUIRE(n >= 1 && nnz >= 0 && rowptr && u && R && (col || nnz == 0), GC_E_INVAL,
+               "bad arguments");
+    GC_REQUIRE(n < INT32_MAX, GC_E_INVAL, "graph too large (n >= 2^31)");
+    DeviceScope ds;
+    int rc;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    const void *drp, *dcol = nullptr, *du;
+    if ((rc = stage_simple(sc, ds.mem_kind, rowptr, (size_t)(n + 1) * 8, &drp))) return rc;
+    if (nnz > 0 && (rc = stage_simple(sc, ds.mem_kind, col, (size_t)nnz * 4, &dcol))) return rc;
+    if ((rc = stage_simple(sc, ds.mem_kind, u, (size_t)n * 4, &du))) return rc;
+    if ((rc = validate_graph(sc, n, nnz, (const int64_t*)drp, (const int32_t*)dcol, ds.stream)))
+        return rc;
+    float* dd = dR;
+    if (dR && ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dd, (size_t)n));
+    const int64_t nblk = (n + kBlock - 1) / kBlock;
+    double *part = nullptr, *dsum = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&part, (size_t)nblk));
+    GC_TRY_HIP(sc.alloc_n(&dsum, 1));
+    GC_TRY_HIP(tv_graph(n, (const int64_t*)drp, (const int32_t*)dcol, (const float*)du,
+                        (float)scale, part, nblk, dd, ds.stream));
+    GC_TRY_HIP(sum_partials_f64(part, nblk, dsum, ds.stream));
+    GC_TRY_HIP(hipMemcpyAsync(R, dsum, sizeof(double), hipMemcpyDeviceToHost, ds.stream));
+    if (dR && ds.mem_kind == GC_MEM_HOST)
+        GC_TRY_HIP(hipMemcpyAsync(dR, dd, (size_t)n * 4, hipMemcpyDeviceToHost, ds.stream));
     GC_TRY_HIP(hipStreamSynchronize(ds.stream));
     return GC_OK;
     GC_GUARD_END

@@ -73,13 +73,19 @@ template <> struct Math<double> {
 // --------------------------------------------------------------------------
 struct U4 { uint32_t x, y, z, w; };
 
+// a ^ b ^ c as one VALU instruction (gfx950 three-input bitwise op; the
+// truth table of XOR3 over inputs 0xF0, 0xCC, 0xAA is 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        uint32_t nx = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
-        uint32_t nz = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        uint32_t nx = xor3((uint32_t)(p1 >> 32), c.y, k0);
+        uint32_t nz = xor3((uint32_t)(p0 >> 32), c.w, k1);
         c.y = (uint32_t)p1;
         c.w = (uint32_t)p0;
         c.x = nx;
@@ -90,9 +96,26 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
-// (2k+1) / 2^24 from the top 23 bits: exact in both precisions, in (0,1).
-template <typename R> __device__ __forceinline__ R uniform01(uint32_t w) {
-    return ((R)(w >> 9) + (R)0.5) * (R)1.1920928955078125e-07;   // 2^-23
+// (2k+1) / 2^24 from the top 23 bits k: exact in both precisions, in (0,1).
+// FP32: one funnel shift places k under the exponent of 1.0, giving
+// x = 1 + k 2^-23 exactly; x - (1 - 2^-24) = (2k+1) 2^-24 is representable
+// (24 significant bits), so the subtraction is exact as well.
+template <typename R> __device__ __forceinline__ R uniform01(uint32_t w);
+template <> __device__ __forceinline__ float uniform01<float>(uint32_t w) {
+    const uint32_t bits = __builtin_amdgcn_alignbit(0x7Fu, w, 9);   // 0x3F800000 | w >> 9
+    return __builtin_bit_cast(float, bits) - 0x1.fffffep-1f;        // 1 - 2^-24
+}
+template <> __device__ __forceinline__ double uniform01<double>(uint32_t w) {
+    return ((double)(w >> 9) + 0.5) * 0x1p-23;
+}
+
+// lo <= x <= hi (x finite, lo <= hi).  FP32: the median of (x, lo, hi) is x
+// exactly when x lies in the box -- one med3 and one compare per coordinate.
+__device__ __forceinline__ bool in_box(float x, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(x, lo, hi) == x;
+}
+__device__ __forceinline__ bool in_box(double x, double lo, double hi) {
+    return x >= lo && x <= hi;
 }
 
 // Draws of one MH step: P normals (Box-Muller on consecutive word pairs) and
@@ -147,21 +170,39 @@ struct AcqDev {
     double te0_d, dte_d;
 };
 
+// Address-space views of device pointers.  Every buffer the kernels touch
+// lives in device global memory; saying so lets the compiler use global
+// (not flat) loads for per-lane data, and scalar loads through the scalar
+// cache for the acquisition tables, which every lane reads at the same
+// index and which no kernel writes.
+template <class T> using gmem_cptr = const __attribute__((address_space(1))) T*;
+template <class T> using cmem_cptr = const __attribute__((address_space(4))) T*;
+template <class T> __device__ __forceinline__ gmem_cptr<T> gload(const T* p) {
+    return (gmem_cptr<T>)p;
+}
+template <class T> __device__ __forceinline__ cmem_cptr<T> cload(const T* p) {
+    return (cmem_cptr<T>)p;
+}
+
 template <typename R> struct AcqView;
 template <> struct AcqView<float> {
-    static __device__ __forceinline__ float te(const AcqDev& a, int m) { return a.te[m]; }
-    static __device__ __forceinline__ float b(const AcqDev& a, int m) { return a.bval[m]; }
+    static __device__ __forceinline__ float te(const AcqDev& a, int m) { return cload(a.te)[m]; }
+    static __device__ __forceinline__ float b(const AcqDev& a, int m) { return cload(a.bval)[m]; }
     static __device__ __forceinline__ float g(const AcqDev& a, int m, int k) {
-        return a.bvec[3 * m + k];
+        return cload(a.bvec)[3 * m + k];
     }
     static __device__ __forceinline__ float te0(const AcqDev& a) { return a.te0; }
     static __device__ __forceinline__ float dte(const AcqDev& a) { return a.dte; }
 };
 template <> struct AcqView<double> {
-    static __device__ __forceinline__ double te(const AcqDev& a, int m) { return a.te_d[m]; }
-    static __device__ __forceinline__ double b(const AcqDev& a, int m) { return a.bval_d[m]; }
+    static __device__ __forceinline__ double te(const AcqDev& a, int m) {
+        return cload(a.te_d)[m];
+    }
+    static __device__ __forceinline__ double b(const AcqDev& a, int m) {
+        return cload(a.bval_d)[m];
+    }
     static __device__ __forceinline__ double g(const AcqDev& a, int m, int k) {
-        return a.bvec_d[3 * m + k];
+        return cload(a.bvec_d)[3 * m + k];
     }
     static __device__ __forceinline__ double te0(const AcqDev& a) { return a.te0_d; }
     static __device__ __forceinline__ double dte(const AcqDev& a) { return a.dte_d; }
@@ -186,8 +227,12 @@ template <typename R, int RECUR> __device__ __forceinline__ bool recur_on(const 
     else return a.uniform != 0;
 }
 
+// Compile-time trip counts unroll fully; a run-time count unrolls by 8, so
+// that the loads of 8 measurements are in flight together.  (The pragma
+// names the template parameter MAXM of the enclosing function.)
 #define GC_FOR_MEAS(m, MAXM, M)                                                 \
-    _Pragma("unroll") for (int m = 0; m < ((MAXM) > 0 ? (MAXM) : (M)); ++m)    \
+    _Pragma("unroll(MAXM > 0 ? MAXM : 8)")                                     \
+    for (int m = 0; m < ((MAXM) > 0 ? (MAXM) : (M)); ++m)                      \
         if ((MAXM) == 0 || EXACT || m < (M))
 
 // --------------------------------------------------------------------------
@@ -468,7 +513,7 @@ template <typename R> struct Dwi2 {
             R x = AcqView<R>::g(a, m, 0) * n[0] + AcqView<R>::g(a, m, 1) * n[1] +
                   AcqView<R>::g(a, m, 2) * n[2];
             R b = AcqView<R>::b(a, m);
-            if (b != bprev) {
+            if (__builtin_expect(b != bprev, 0)) {   // uniform: a scalar branch
                 ball = ((R)1 - th[0]) * Math<R>::exp(-b * th[2]);
                 bprev = b;
             }
@@ -490,7 +535,7 @@ template <typename R> struct Dwi2 {
             R b = AcqView<R>::b(a, m);
             R x = g0 * n[0] + g1 * n[1] + g2 * n[2];
             R Ea = Math<R>::exp(-b * th[1] * x * x);
-            if (b != bprev) {
+            if (__builtin_expect(b != bprev, 0)) {   // uniform: a scalar branch
                 Ee = Math<R>::exp(-b * th[2]);
                 bprev = b;
             }

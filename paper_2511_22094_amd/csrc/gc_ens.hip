@@ -42,8 +42,8 @@ struct YGlobE {
     const float* y;
     int64_t n, v;
     int M;
-    __device__ __forceinline__ float re(int m) const { return y[(int64_t)m * n + v]; }
-    __device__ __forceinline__ float im(int m) const { return y[(int64_t)(M + m) * n + v]; }
+    __device__ __forceinline__ float re(int m) const { return gload(y)[(int64_t)m * n + v]; }
+    __device__ __forceinline__ float im(int m) const { return gload(y)[(int64_t)(M + m) * n + v]; }
 };
 
 __device__ __forceinline__ int first_keep_e(int t0, int burnin, int thin) {
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restri
                 for (int p = 0; p < P; ++p) {
                     const R xj = Xv[(size_t)j * P + p];
                     Y[p] = xj + z * (Xv[(size_t)k * P + p] - xj);
-                    inb = inb && (Y[p] >= lbE<R>(J, p)) && (Y[p] <= ubE<R>(J, p));
+                    inb &= in_box(Y[p], lbE<R>(J, p), ubE<R>(J, p));
                 }
                 R ev[P];
 #pragma unroll

@@ -58,6 +58,13 @@ struct FitJob {
     int loss_p;              // 1 or 2
     int optimizer;           // 0 Adam, 1 SGDM, 2 RMSProp
     uint32_t tv_mask;
+    int tv_kind;             // 0 anisotropic grid, 1 isotropic grid, 2 graph
+    const int64_t* g_rowptr; // graph TV: CSR offsets [n + 1] over compact voxels
+    const int32_t* g_col;    // graph TV: neighbour compact indices
+    uint32_t prior_mask;     // prior (Eq. 6) on these parameters
+    float scale_prior;       // prior_lambda / N
+    const float* mu;         // [P][n] prior means (compacted) or nullptr
+    const float* sigma;      // [P][n] prior SDs (compacted) or nullptr
     float lb[kMaxP], rng[kMaxP];   // theta = lb + rng * u
     float u0[kMaxP];         // start in u units when there is no map
     float lr, beta1, beta2, eps, momentum, rho;
@@ -120,6 +127,14 @@ hipError_t loss_vjp(int kind, const AcqDev& a, const float* theta, const float* 
                     hipStream_t st);
 hipError_t tv_grid(int nx, int ny, int nz, const uint8_t* mask, const float* u, int dim,
                    float scale, double* partial, int64_t nblk, float* dR, hipStream_t st);
+hipError_t tv_grid_iso(int nx, int ny, int nz, const uint8_t* mask, const float* u, int dim,
+                       float scale, double* partial, int64_t nblk, float* dR, hipStream_t st);
+hipError_t tv_graph(int64_t n, const int64_t* rowptr, const int32_t* col, const float* u,
+                    float scale, double* partial, int64_t nblk, float* dR, hipStream_t st);
+// flag |= 1 unless rowptr[0] = 0, rowptr non-decreasing, rowptr[n] = nnz and
+// every col[k] (k < nnz) in [0, n)
+hipError_t check_graph(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
+                       int* flag, hipStream_t st);
 
 // layout and reductions (gc_pack.hip)
 struct PackPlan {
@@ -150,5 +165,6 @@ hipError_t philox_uniform_normal(uint64_t seed, const uint32_t* ctr, int64_t n, 
                                  void* out_u, void* out_z, hipStream_t s);
 hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t check_positive(const float* p, int64_t n, int* flag, hipStream_t s);
 
 }  // namespace gc

@@ -24,8 +24,8 @@ struct YGlob {
     int64_t n;
     int64_t v;
     int M;
-    __device__ __forceinline__ float re(int m) const { return y[(int64_t)m * n + v]; }
-    __device__ __forceinline__ float im(int m) const { return y[(int64_t)(M + m) * n + v]; }
+    __device__ __forceinline__ float re(int m) const { return gload(y)[(int64_t)m * n + v]; }
+    __device__ __forceinline__ float im(int m) const { return gload(y)[(int64_t)(M + m) * n + v]; }
 };
 
 template <typename R> __device__ __forceinline__ R lbR(const MhJob& J, int p);
@@ -144,6 +144,9 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
         lo[p] = lbR<R>(J, p);
         hi[p] = ubR<R>(J, p);
         st[p] = stepR<R>(J, p);
+        // keep the upper bounds in vector registers: the box test takes both
+        // bounds in one instruction, which reads at most one scalar register
+        if constexpr (sizeof(R) == 4) asm volatile("" : "+v"(hi[p]));
     }
     const R w = J.w ? (R)J.w[v] : (R)1;
     const R nscale = -(inv2s2R<R>(J) * w * w);
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             thp[p] = th[p] + st[p] * z[p];
-            inb = inb && (thp[p] >= lo[p]) && (thp[p] <= hi[p]);
+            inb &= in_box(thp[p], lo[p], hi[p]);
         }
         // out-of-box proposals are rejected; evaluate at the current state
         // instead of branching so the wave stays converged
@@ -253,8 +256,8 @@ __global__ __launch_bounds__(kBlock) void mh_finalize_kernel(const MhJob* __rest
 int mh_pick_maxm(int kind, int M) {
     static const int mono[] = {12, 16, 32};
     static const int gre[] = {12, 24, 32};
-    static const int dwi[] = {32, 64, 96};
-    const int* list = kind == GRE3 ? gre : (kind == DWI2 ? dwi : mono);
+    if (kind == DWI2) return 0;
+    const int* list = kind == GRE3 ? gre : mono;
     if (kind == LINEAR3) return M <= 12 ? 12 : (M <= 16 ? 16 : 0);
     for (int i = 0; i < 3; ++i)
         if (M <= list[i]) return list[i];
@@ -313,6 +316,11 @@ static hipError_t chunk_f32(int variant, const MhJob* jobs, const BlkMap* map, i
 // exactly MAXM measurements and -- for the exponential-decay models -- equally
 // spaced echoes (the recurrence then applies unconditionally).
 int mh_pick_variant(int kind, int M, int uniform) {
+    // dwi2 reads its data from memory: with up to 96 measurements per lane in
+    // registers (and the straight-line form's hoisted acquisition values) the
+    // kernel runs at one or two waves per SIMD, which measured 1.2x (register
+    // loop) to 5.8x (straight line) slower than the memory-read loop
+    if (kind == DWI2) return 0;
     const int maxm = mh_pick_maxm(kind, M);
     const bool rec_model = kind == MONOEXP_T2S || kind == MONOEXP_R2S || kind == GRE3;
     const bool exact = maxm == M && (!rec_model || uniform);
@@ -335,7 +343,7 @@ hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkM
         case MONOEXP_T2S: return chunk_f32<MONOEXP_T2S, 12, 16, 32>(maxm, jobs, map, nblk, s);
         case MONOEXP_R2S: return chunk_f32<MONOEXP_R2S, 12, 16, 32>(maxm, jobs, map, nblk, s);
         case GRE3: return chunk_f32<GRE3, 12, 24, 32>(maxm, jobs, map, nblk, s);
-        case DWI2: return chunk_f32<DWI2, 32, 64, 96>(maxm, jobs, map, nblk, s);
+        case DWI2: return chunk_t<DWI2, float, 0>(jobs, map, nblk, s);   // see mh_pick_variant
         case LINEAR3: return chunk_f32<LINEAR3, 12, 16, 16>(maxm, jobs, map, nblk, s);
     }
     return hipErrorInvalidValue;

@@ -248,6 +248,18 @@ hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// flag |= 1 if any of p[0..n) is not a finite value > 0
+__global__ void check_positive_kernel(const float* __restrict__ p, int64_t n, int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n && !(p[i] > 0.f && p[i] < INFINITY)) atomicOr(flag, 1);
+}
+hipError_t check_positive(const float* p, int64_t n, int* flag, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(check_positive_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, p, n, flag);
+    return hipGetLastError();
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = v;

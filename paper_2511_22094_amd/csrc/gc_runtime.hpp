@@ -118,7 +118,20 @@ struct Packed {
 int pack_problem(Scratch& sc, const gc_model* m, const gc_volume* data, const uint8_t* mask,
                  const float* weights, const float* x0map, int mem_kind, Packed* out);
 
+// Prior maps (Eq. 6) of a fit, gathered to [P][n] over the mask; sigma must be
+// finite and > 0, mu finite (GC_E_INVAL / GC_E_NONFINITE otherwise).  Both
+// stay nullptr when the prior is off.
+int pack_prior(Scratch& sc, const gc_model* m, const gc_adam_hyper* h, const Packed& pk,
+               int mem_kind, float** mu, float** sigma);
+// Graph adjacency of a fit with graph TV, in device memory and checked
+// (GC_E_INVAL unless it is a valid CSR over the n masked voxels).
+int pack_graph(Scratch& sc, const gc_adam_hyper* h, int64_t n, int mem_kind,
+               const int64_t** rowptr, const int32_t** col);
+int validate_graph(Scratch& sc, int64_t n, int64_t nnz, const int64_t* rowptr,
+                   const int32_t* col, hipStream_t s);
+
 int validate_bounds(const gc_model* m, const gc_bounds* b);
+int validate_adam(const gc_model* m, const gc_adam_hyper* h);
 int validate_volume(const gc_model* m, const gc_volume* v);
 
 // descriptor builders shared by the synchronous calls and the server

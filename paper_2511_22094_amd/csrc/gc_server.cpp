@@ -153,6 +153,10 @@ size_t footprint_of(const gc_model* m, const gc_job& j, int64_t G, int64_t n) {
     } else {
         b += (size_t)n * m->P * 4 * 5 + (size_t)n * 24 + (size_t)G * m->P * 4;
         const bool each = j.adam.tol > 0 || j.adam.conv_value > 0;
+        if (j.adam.prior_lambda > 0 && j.adam.prior_mask)
+            b += (size_t)(G + n) * m->P * 8;   // staged and gathered prior maps
+        if (j.adam.lambda > 0 && j.adam.tv_mask && j.adam.tv_kind == GC_TV_GRAPH)
+            b += (size_t)(n + 1) * 8 + (size_t)std::max<int64_t>(j.adam.graph_nnz, 0) * 4;
         b += (size_t)((n + kBlock - 1) / kBlock) * (each ? j.adam.n_iter : 1) * 4 +
              (size_t)j.adam.n_iter * 8;
     }
@@ -234,6 +238,15 @@ static int prepare_job(gc_server* S, Job* J) {
         q.y = J->pk.y;
         q.w = J->pk.w;
         q.x0map = J->pk.x0;
+        float *pmu = nullptr, *psg = nullptr;
+        if ((rc = pack_prior(sc, m, &h, J->pk, GC_MEM_HOST, &pmu, &psg))) return rc;
+        q.mu = pmu;
+        q.sigma = psg;
+        const int64_t* grp = nullptr;
+        const int32_t* gcol = nullptr;
+        if ((rc = pack_graph(sc, &h, n, GC_MEM_HOST, &grp, &gcol))) return rc;
+        q.g_rowptr = grp;
+        q.g_col = gcol;
         const size_t np = (size_t)std::max<int64_t>(n, 1) * P;
         GC_TRY_HIP(sc.alloc_n(&J->u0, np));
         GC_TRY_HIP(sc.alloc_n(&J->u1, np));
@@ -248,7 +261,7 @@ static int prepare_job(gc_server* S, Job* J) {
         J->maxm = fit_pick_maxm(m->kind, m->M);
         if (J->step_path) {
             int32_t* nbr = nullptr;
-            if (q.tv_mask) {
+            if (q.tv_mask && q.tv_kind != GC_TV_GRAPH) {
                 GC_TRY_HIP(sc.alloc_n(&nbr, (size_t)std::max<int64_t>(n, 1) * 6));
                 GC_TRY_HIP(build_neighbours(J->pk.c2g, J->pk.g2c, n, J->spec.data.nx, J->spec.data.ny,
                                             J->spec.data.nz, h.tv_dim, nbr, S->prep));
@@ -827,10 +840,7 @@ int gc_submit(gc_server* S, const gc_job* job, uint64_t* job_id) {
         } else if (job->kind == GC_JOB_FIT) {
             const gc_adam_hyper& h = job->adam;
             GC_REQUIRE(job->out_maps, GC_E_INVAL, "fit job needs out_maps");
-            GC_REQUIRE(h.n_iter >= 1 && (h.loss == 1 || h.loss == 2) && h.optimizer >= 0 &&
-                           h.optimizer <= 2 && h.lr > 0 && (h.tv_dim == 2 || h.tv_dim == 3) &&
-                           (h.tv_mask >> P) == 0,
-                       GC_E_INVAL, "bad fit hyper-parameters");
+            if ((rc = validate_adam(m, &h))) return rc;
         } else {
             set_error("unknown job kind");
             return GC_E_INVAL;

@@ -20,9 +20,11 @@ std::map<std::string, Tot> g_tot;
 }  // namespace
 
 bool timing_on() { return g_on.load() != 0; }
+int timing_every() { const int k = g_on.load(); return k > 0 ? k : 1; }
 
 void LaunchTimer::begin() {
     if (!timing_on()) return;
+    if (count++ % timing_every() != 0) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, s);
@@ -72,7 +74,7 @@ LaunchTimer::~LaunchTimer() {
 extern "C" {
 
 int gc_timing_enable(int on) {
-    gc::g_on.store(on ? 1 : 0);
+    gc::g_on.store(on > 0 ? on : 0);
     return GC_OK;
 }
 

@@ -8,6 +8,7 @@
 namespace gc {
 
 bool timing_on();
+int timing_every();   // time every k-th launch (k >= 1) while on
 // Brackets launches: begin() before, end() after; flush() after the stream
 // has been synchronised adds the elapsed times to the family's total.
 struct LaunchTimer {
@@ -15,6 +16,7 @@ struct LaunchTimer {
     hipStream_t s;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     hipEvent_t pending = nullptr;
+    int64_t count = 0;       // launches seen (timed or not)
     LaunchTimer(const char* fam, hipStream_t st) : family(fam), s(st) {}
     void begin();
     void end();

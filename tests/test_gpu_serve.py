@@ -41,6 +41,29 @@ def _job_specs():
     specs.append(("fit", d, y, dict(n_iter=60, lam=1e-3, tv_params=(0, 1, 2), tv_dim=3)))
     d, y = data("gre3", (3, 5, 5), 6, 0.01)
     specs.append(("fit", d, y, dict(n_iter=300, tol=1e-6)))
+    # regularisers: graph TV with the prior (step path), isotropic 2D TV, and
+    # the prior alone (fused path)
+    from graphs import grid_graph
+    rng = np.random.default_rng(77)
+
+    def prior_maps(d):
+        P = d.lb.size
+        r = (d.ub - d.lb)[:, None, None, None]
+        mu = (d.lb[:, None, None, None] + r * rng.uniform(0.3, 0.7, (P,) + d.mask.shape))
+        return mu.astype(np.float32), (0.2 * r * np.ones((P,) + d.mask.shape)).astype(np.float32)
+
+    d, y = data("dwi2", (4, 5, 6), 7, 0.02, acq=acq, block=3)
+    mu, sg = prior_maps(d)
+    specs.append(("fit", d, y, dict(n_iter=60, lam=1e-3, tv_params=(0, 1, 2), tv_kind="graph",
+                                    graph=grid_graph(d.mask, 3), prior_lam=1e-3,
+                                    prior_params=(1,), prior_mu=mu, prior_sigma=sg)))
+    d, y = data("dwi2", (3, 6, 6), 8, 0.02, acq=acq, block=3)
+    specs.append(("fit", d, y, dict(n_iter=40, lam=1e-3, tv_params=(0,), tv_dim=2,
+                                    tv_kind="iso")))
+    d, y = data("monoexp_t2s", (3, 6, 6), 9, 0.02)
+    mu, sg = prior_maps(d)
+    specs.append(("fit", d, y, dict(n_iter=150, prior_lam=1e-3, prior_params=(0, 1),
+                                    prior_mu=mu, prior_sigma=sg)))
     return specs
 
 
