@@ -175,6 +175,51 @@ def copy_leg(torch, mib=256, reps=3):
     return dict(bytes_read=n * 4, bytes_written=n * 4, launches=reps)
 
 
+def sweep(g, torch, repeats=10):
+    """Throughput against volume size (cf. the paper's scaling figure): for each
+    model and N in {1e2, 1e3, 1e4, 1e5, 2.5e5, 1e6} voxels, the median wall
+    time of one whole call (pack, solve, unpack; data resident on the GPU) for
+    MH (4 chains x 1000 iterations, burn-in 100, thin 10, FP32) and Adam
+    (200 iterations, no TV).  Prints one JSON line per point."""
+    from paper_2511_22094_amd import synth
+    acqs = {"monoexp_t2s": synth.Acq(te=synth.echo_times(2.0, 4.0, 12)),
+            "gre3": synth.Acq(te=synth.echo_times(2.0, 2.0, 24)),
+            "dwi2": synth.dwi_acq(np.random.default_rng(1002))}
+    sigma = {"monoexp_t2s": 0.01, "gre3": 0.01, "dwi2": 0.02}
+    dev = torch.device("cuda:0")
+    for model, acq in acqs.items():
+        m = g.Model.from_acq(model, acq)
+        for N in (100, 1000, 10000, 100000, 250000, 1000000):
+            d = synth.make_draw(model, (1, 1, N), 7, sigma[model], acq=acq)
+            s_ = g.gc_model_forward(m, torch.tensor(d.truth, dtype=torch.float32, device=dev))
+            y = (s_ + d.sigma * torch.from_numpy(d.noise).to(dev)).reshape(-1, 1, 1, N).contiguous()
+            P = d.lb.size
+            mean = torch.empty((P, 1, 1, N), dtype=torch.float64, device=dev)
+            std = torch.empty_like(mean)
+            maps = torch.empty((P, 1, 1, N), dtype=torch.float32, device=dev)
+            runs = {
+                "mh": (lambda: g.gc_mcmc(m, y, None, d.lb, d.ub, 4, 1000, 100, 10, sigma=d.sigma,
+                                         step=synth.MH_STEP[model], seed=1, accept=False,
+                                         out_mean=mean, out_std=std), N * 4 * 1000),
+                "adam": (lambda: g.gc_fit_askadam(m, y, None, d.lb, d.ub, n_iter=200, out=maps),
+                         N * 200),
+            }
+            for solver, (fn, units) in runs.items():
+                fn()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(repeats):
+                    t0 = time.perf_counter()
+                    fn()
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                t = float(np.median(ts))
+                print(json.dumps({"sweep": solver, "model": model, "voxels": N,
+                                  "median_s": t, "mean_s": float(np.mean(ts)),
+                                  "voxel_iter_per_s": units / t}), flush=True)
+            del y, s_, mean, std, maps
+
+
 SERVE_MODELS = {
     "monoexp_t2s": 0.01,
     "gre3": 0.01,
@@ -312,6 +357,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving leg on the full 256-job trace (voxels up to 1e6)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="throughput against volume size per model (no headline line)")
     ap.add_argument("--profile-only", default=None,
                     help="comma list of mh, adam, copy: run only these legs once each (no "
                          "warm-up, no headline line) for hardware counter collection")
@@ -323,6 +370,9 @@ def main():
     import torch
     from paper_2511_22094_amd import lib
     g = lib()
+    if args.sweep:
+        sweep(g, torch)
+        return
     if args.profile_only:
         legs = [x.strip() for x in args.profile_only.split(",") if x.strip()]
         rep = {}

@@ -166,7 +166,7 @@ typedef struct {
     double rho;            /* RMSProp squared-gradient decay (0.9) */
     int n_iter;            /* maximum iterations (>= 1) */
     int loss;              /* 1 = L1, 2 = L2 */
-    const float *weights;  /* [nz][ny][nx] w_v (exec memory) or NULL = 1 */
+    const float *weights;  /* [nz][ny][nx] w_v >= 0 (exec memory) or NULL = 1 */
     double lambda;         /* TV weight (0 = off) */
     uint32_t tv_mask;      /* bit p set: TV on parameter p */
     int tv_dim;            /* 2 or 3 */

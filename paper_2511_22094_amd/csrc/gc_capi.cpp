@@ -170,12 +170,20 @@ int model_acq(const gc_model* m, int device, AcqDev* out) {
             }
         }
     }
+    // runs of consecutive equal b values (shells in acquisition order)
+    std::vector<int32_t> run_end;
+    for (int j = 1; j < M; ++j)
+        if (!m->bval.empty() && m->bval[j] != m->bval[j - 1]) run_end.push_back(j);
+    run_end.push_back(M);
     const size_t fb = f.size() * sizeof(float), db = d.size() * sizeof(double);
+    const size_t rb = run_end.size() * sizeof(int32_t);
     const size_t off = (fb + 255) / 256 * 256;
+    const size_t off2 = off + (db + 255) / 256 * 256;
     void* buf = nullptr;
-    GC_TRY_HIP(hipMalloc(&buf, off + db));
+    GC_TRY_HIP(hipMalloc(&buf, off2 + rb));
     GC_TRY_HIP(hipMemcpy(buf, f.data(), fb, hipMemcpyHostToDevice));
     GC_TRY_HIP(hipMemcpy((char*)buf + off, d.data(), db, hipMemcpyHostToDevice));
+    GC_TRY_HIP(hipMemcpy((char*)buf + off2, run_end.data(), rb, hipMemcpyHostToDevice));
     AcqDev a{};
     float* fp = (float*)buf;
     double* dp = (double*)((char*)buf + off);
@@ -191,6 +199,8 @@ int model_acq(const gc_model* m, int device, AcqDev* out) {
     a.dte = (float)m->dte;
     a.te0_d = m->te0;
     a.dte_d = m->dte;
+    a.run_end = (const int32_t*)((char*)buf + off2);
+    a.nrun = (int)run_end.size();
     m->dev[device] = gc_model::DevAcq{buf, a};
     *out = a;
     return GC_OK;

@@ -26,9 +26,12 @@ enum ModelKind { MONOEXP_T2S = 0, MONOEXP_R2S = 1, GRE3 = 2, DWI2 = 3, LINEAR3 =
 template <typename R> struct Math;
 
 template <> struct Math<float> {
+    static constexpr float kLog2e = 1.44269504088896341f;
     static __device__ __forceinline__ float exp(float x) {
-        return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+        return __builtin_amdgcn_exp2f(x * kLog2e);
     }
+    // 2^x: for exponents whose log2(e) factor is folded into a constant
+    static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
     static __device__ __forceinline__ float ln(float x) {
         return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
     }
@@ -168,6 +171,10 @@ struct AcqDev {
     int uniform;
     float te0, dte;
     double te0_d, dte_d;
+    // runs of consecutive measurements with equal b (a shell, in acquisition
+    // order): run r ends (exclusive) at run_end[r]; one run when there is no b
+    const int* run_end;
+    int nrun;
 };
 
 // Address-space views of device pointers.  Every buffer the kernels touch
@@ -506,6 +513,38 @@ template <typename R> struct Dwi2 {
         R n[8];
         dir(th, n);
         R acc = 0;
+        if constexpr (MAXM == 0) {
+            // run-time loop: shell by shell, the ball term once per shell and
+            // no branch in the measurement loop (same values as below)
+            int m = 0;
+            for (int r = 0; r < a.nrun; ++r) {
+                const int mend = cload(a.run_end)[r];
+                const R b = AcqView<R>::b(a, m);
+                const R ball = ((R)1 - th[0]) * Math<R>::exp(-b * th[2]);
+                if constexpr (sizeof(R) == 4) {
+                    // FP32: log2(e) folded into the shell constant, one exp2
+                    const R cb = -b * th[1] * Math<R>::kLog2e;
+#pragma unroll 8
+                    for (; m < mend; ++m) {
+                        R x = AcqView<R>::g(a, m, 0) * n[0] + AcqView<R>::g(a, m, 1) * n[1] +
+                              AcqView<R>::g(a, m, 2) * n[2];
+                        R s = th[0] * Math<R>::exp2(cb * x * x) + ball;
+                        R rr = (R)y.re(m) - s;
+                        acc += rr * rr;
+                    }
+                } else {
+#pragma unroll 8
+                    for (; m < mend; ++m) {
+                        R x = AcqView<R>::g(a, m, 0) * n[0] + AcqView<R>::g(a, m, 1) * n[1] +
+                              AcqView<R>::g(a, m, 2) * n[2];
+                        R s = th[0] * Math<R>::exp(-b * th[1] * x * x) + ball;
+                        R rr = (R)y.re(m) - s;
+                        acc += rr * rr;
+                    }
+                }
+            }
+            return acc;
+        }
         // the ball term depends on b only: on a shell (consecutive equal b,
         // a uniform test) it is reused instead of recomputed -- same values
         R bprev = (R)-1, ball = 0;
@@ -528,26 +567,88 @@ template <typename R> struct Dwi2 {
         R n[8];
         dir(th, n);
         R gf = 0, gda = 0, gde = 0, gn0 = 0, gn1 = 0, gn2 = 0;
-        R bprev = (R)-1, Ee = 0;   // ball term reused along a shell (see sse)
-        GC_FOR_MEAS(m, MAXM, a.M) {
-            R g0 = AcqView<R>::g(a, m, 0), g1 = AcqView<R>::g(a, m, 1),
-              g2 = AcqView<R>::g(a, m, 2);
-            R b = AcqView<R>::b(a, m);
-            R x = g0 * n[0] + g1 * n[1] + g2 * n[2];
-            R Ea = Math<R>::exp(-b * th[1] * x * x);
-            if (__builtin_expect(b != bprev, 0)) {   // uniform: a scalar branch
-                Ee = Math<R>::exp(-b * th[2]);
-                bprev = b;
+        if constexpr (MAXM == 0 && sizeof(R) == 4) {
+            // Shell by shell with the shell constants b, Ee factored out of the
+            // sums: per measurement q = d Ea, then
+            //   gf  += q - Ee d,   gda += b q x^2,   gde += b Ee d,
+            //   gn  += b q x g,
+            // where the b and Ee products are applied once per shell.
+            int m = 0;
+            for (int r = 0; r < a.nrun; ++r) {
+                const int mend = cload(a.run_end)[r];
+                const R b = AcqView<R>::b(a, m);
+                const R Ee = Math<R>::exp(-b * th[2]);
+                const R cb = -b * th[1] * Math<R>::kLog2e;
+                const R ball = ((R)1 - th[0]) * Ee;
+                R sq = 0, sd = 0, sx = 0, s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll 8
+                for (; m < mend; ++m) {
+                    R g0 = AcqView<R>::g(a, m, 0), g1 = AcqView<R>::g(a, m, 1),
+                      g2 = AcqView<R>::g(a, m, 2);
+                    R x = g0 * n[0] + g1 * n[1] + g2 * n[2];
+                    R Ea = Math<R>::exp2(cb * x * x);
+                    R dj = d.re(m, th[0] * Ea + ball);
+                    R q = dj * Ea;
+                    sq += q;
+                    sd += dj;
+                    R qx = q * x;
+                    sx += qx * x;
+                    s0 += qx * g0;
+                    s1 += qx * g1;
+                    s2 += qx * g2;
+                }
+                gf += sq - Ee * sd;
+                gda += b * sx;
+                gde += b * Ee * sd;
+                gn0 += b * s0;
+                gn1 += b * s1;
+                gn2 += b * s2;
             }
-            R dj = d.re(m, th[0] * Ea + ((R)1 - th[0]) * Ee);
-            gf += dj * (Ea - Ee);
-            R t = dj * b * Ea;      // d * b * Ea
-            gda += t * x * x;
-            gde += dj * b * Ee;
-            R tx = t * x;
-            gn0 += tx * g0;
-            gn1 += tx * g1;
-            gn2 += tx * g2;
+        } else if constexpr (MAXM == 0) {
+            int m = 0;
+            for (int r = 0; r < a.nrun; ++r) {
+                const int mend = cload(a.run_end)[r];
+                const R b = AcqView<R>::b(a, m);
+                const R Ee = Math<R>::exp(-b * th[2]);
+#pragma unroll 8
+                for (; m < mend; ++m) {
+                    R g0 = AcqView<R>::g(a, m, 0), g1 = AcqView<R>::g(a, m, 1),
+                      g2 = AcqView<R>::g(a, m, 2);
+                    R x = g0 * n[0] + g1 * n[1] + g2 * n[2];
+                    R Ea = Math<R>::exp(-b * th[1] * x * x);
+                    R dj = d.re(m, th[0] * Ea + ((R)1 - th[0]) * Ee);
+                    gf += dj * (Ea - Ee);
+                    R t = dj * b * Ea;
+                    gda += t * x * x;
+                    gde += dj * b * Ee;
+                    R tx = t * x;
+                    gn0 += tx * g0;
+                    gn1 += tx * g1;
+                    gn2 += tx * g2;
+                }
+            }
+        } else {
+            R bprev = (R)-1, Ee = 0;   // ball term reused along a shell (see sse)
+            GC_FOR_MEAS(m, MAXM, a.M) {
+                R g0 = AcqView<R>::g(a, m, 0), g1 = AcqView<R>::g(a, m, 1),
+                  g2 = AcqView<R>::g(a, m, 2);
+                R b = AcqView<R>::b(a, m);
+                R x = g0 * n[0] + g1 * n[1] + g2 * n[2];
+                R Ea = Math<R>::exp(-b * th[1] * x * x);
+                if (__builtin_expect(b != bprev, 0)) {   // uniform: a scalar branch
+                    Ee = Math<R>::exp(-b * th[2]);
+                    bprev = b;
+                }
+                R dj = d.re(m, th[0] * Ea + ((R)1 - th[0]) * Ee);
+                gf += dj * (Ea - Ee);
+                R t = dj * b * Ea;      // d * b * Ea
+                gda += t * x * x;
+                gde += dj * b * Ee;
+                R tx = t * x;
+                gn0 += tx * g0;
+                gn1 += tx * g1;
+                gn2 += tx * g2;
+            }
         }
         g[0] = gf;
         g[1] = -th[0] * gda;
