@@ -214,6 +214,14 @@ int gc_fit_askadam(const gc_model *model, const gc_volume *data, const uint8_t *
  * Retained samples per chain K = (n_iter - burnin) / thin (>= 2 required).
  * gc_burnin_from_ratio mirrors the paper's burn-in ratio: floor(r n_iter).
  *
+ * Resume (MH only): with t_start > 0 the call runs steps t_start..n_iter-1
+ * of the same random streams, starting from init_state (and init_logl),
+ * e.g. the final_state / final_logl of a run that stopped at t_start: the
+ * chains then continue bit for bit as if never interrupted.  Retention keeps
+ * the absolute rule above; the moments, samples (K = retained steps in
+ * [t_start, n_iter), >= 2) and accept counts cover this call's steps only,
+ * so the moments of consecutive calls combine by the pooled-variance rule.
+ *
  * Sampler GC_SAMPLER_ENSEMBLE runs the affine-invariant ensemble sampler
  * (Goodman & Weare 2010, stretch move with scale `stretch`, n_walkers
  * walkers per voxel, two half-ensembles updated in turn); n_chains is then
@@ -234,8 +242,14 @@ typedef struct {
     int n_walkers;         /* ensemble size (even, >= 4) */
     double stretch;        /* ensemble stepSize a > 1 (default 2) */
     int chunk_iters;       /* iterations per launch (0 = library default) */
-    double *final_state;   /* [C][P][n_masked] last states (exec memory) or NULL */
+    double *final_state;   /* [P][C][n_masked] last states (exec memory) or NULL */
     double *final_logl;    /* [C][n_masked] last log-likelihoods or NULL */
+    int t_start;           /* first step of this call (resume; 0 = fresh run) */
+    const double *init_state; /* [P][C][n_masked] chain states at t_start (exec
+                                 memory, inside the bounds); required when
+                                 t_start > 0, else overrides x0_mode */
+    const double *init_logl;  /* [C][n_masked] their log-likelihoods (exec
+                                 memory) or NULL = recomputed */
 } gc_mcmc_hyper;
 
 void gc_mcmc_defaults(gc_mcmc_hyper *h);

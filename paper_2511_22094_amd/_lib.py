@@ -93,7 +93,8 @@ class gc_mcmc_hyper(ctypes.Structure):
     _fields_ = [("sigma", c_double), ("step", c_void_p), ("seed", c_uint64), ("x0_mode", c_int),
                 ("weights", c_void_p), ("precision", c_int), ("sampler", c_int),
                 ("n_walkers", c_int), ("stretch", c_double), ("chunk_iters", c_int),
-                ("final_state", c_void_p), ("final_logl", c_void_p)]
+                ("final_state", c_void_p), ("final_logl", c_void_p), ("t_start", c_int),
+                ("init_state", c_void_p), ("init_logl", c_void_p)]
 
 
 class gc_server_cfg(ctypes.Structure):
@@ -387,9 +388,13 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
 def gc_mcmc(model: Model, y, mask, lb, ub, n_chains, n_iter, burnin, thin, *, sigma,
             step=None, seed=0, x0=None, x0_map=None, x0_mode="midpoint", weights=None,
             precision="fp32", sampler="mh", n_walkers=50, stretch=2.0, chunk_iters=0,
-            samples=False, accept=True, final_state=False, out_mean=None, out_std=None):
+            samples=False, accept=True, final_state=False, out_mean=None, out_std=None,
+            t_start=0, init_state=None, init_logl=None):
     """Returns dict(mean, std [P, nz, ny, nx] float64, accept [C, nz, ny, nx],
-    samples [C, K, P, n_masked] float32 or None, final_state [P, C, n], final_logl [C, n])."""
+    samples [C, K, P, n_masked] float32 or None, final_state [P, C, n], final_logl [C, n]).
+
+    Resume: t_start > 0 with init_state [P, C, n] (and init_logl [C, n]), e.g. the
+    final_state / final_logl of a call that ran up to step t_start."""
     a = _Args()
     nx, ny, nz = _shape3(y, model)
     vol = gc_volume(nx, ny, nz, a.ptr(y, np.float32))
@@ -411,8 +416,11 @@ def gc_mcmc(model: Model, y, mask, lb, ub, n_chains, n_iter, burnin, thin, *, si
     h.n_walkers = n_walkers
     h.stretch = stretch
     h.chunk_iters = chunk_iters
+    h.t_start = int(t_start)
+    h.init_state = a.ptr(init_state, np.float64)
+    h.init_logl = a.ptr(init_logl, np.float64)
     C = n_walkers if sampler == "ensemble" else n_chains
-    K = (n_iter - burnin) // thin
+    K = (n_iter - burnin) // thin - (max(t_start - burnin, 0) // thin)
     if mask is None:
         n = nx * ny * nz
     elif _is_torch(mask):

@@ -353,7 +353,11 @@ int fill_mh_job(const gc_model* m, const gc_bounds* b, const gc_mcmc_hyper* h, i
     J->k1 = (uint32_t)(h->seed >> 32);
     J->burnin = burnin;
     J->thin = thin;
-    J->K = (n_iter - burnin) / thin;
+    // retained steps t >= burnin with (t - burnin + 1) % thin == 0: those
+    // before step T number max(0, T - burnin) / thin
+    auto kept_before = [&](int T) { return T > burnin ? (T - burnin) / thin : 0; };
+    J->k_base = kept_before(h->t_start);
+    J->K = kept_before(n_iter) - J->k_base;
     J->x0_mode = h->x0_mode;
     for (int p = 0; p < m->P; ++p) {
         const double lo = b->lb[p], hi = b->ub[p];
@@ -821,8 +825,18 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
     GC_REQUIRE(n_chains >= 1 && n_chains <= 65535, GC_E_INVAL, "n_chains must be in 1..65535");
     GC_REQUIRE(n_iter >= 1 && burnin >= 0 && burnin < n_iter && thin >= 1, GC_E_INVAL,
                "need n_iter >= 1, 0 <= burnin < n_iter, thin >= 1");
-    GC_REQUIRE((n_iter - burnin) / thin >= 2, GC_E_INVAL,
-               "fewer than 2 retained samples per chain");
+    GC_REQUIRE(hyper->t_start >= 0 && hyper->t_start < n_iter, GC_E_INVAL,
+               "t_start must be in [0, n_iter)");
+    GC_REQUIRE(hyper->t_start == 0 || hyper->init_state, GC_E_INVAL,
+               "resuming at t_start > 0 needs init_state");
+    GC_REQUIRE(!ens || (hyper->t_start == 0 && !hyper->init_state), GC_E_INVAL,
+               "resume (t_start, init_state) is for the MH sampler");
+    {
+        const int k_all = (n_iter - burnin) / thin;
+        const int k_before = hyper->t_start > burnin ? (hyper->t_start - burnin) / thin : 0;
+        GC_REQUIRE(k_all - k_before >= 2, GC_E_INVAL,
+                   "fewer than 2 retained samples per chain in this call");
+    }
     GC_REQUIRE(hyper->precision == GC_PREC_FP32 || hyper->precision == GC_PREC_FP64, GC_E_INVAL,
                "precision must be GC_PREC_FP32 or GC_PREC_FP64");
     GC_REQUIRE(hyper->x0_mode >= 0 && hyper->x0_mode <= 2, GC_E_INVAL, "bad x0_mode");
@@ -846,6 +860,17 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
     J.w = pk.w;
     J.x0map = pk.x0;
     J.n = n;
+    if (hyper->init_state && n > 0) {
+        const void *dis = nullptr, *dil = nullptr;
+        if ((rc = stage_in(sc, hyper->init_state, (size_t)P * C * n * sizeof(double), ds.mem_kind,
+                           &dis)))
+            return rc;
+        if ((rc = stage_in(sc, hyper->init_logl, (size_t)C * n * sizeof(double), ds.mem_kind,
+                           &dil)))
+            return rc;
+        J.init_state = (const double*)dis;
+        J.init_logl = (const double*)dil;
+    }
     const size_t rs = fp64 ? sizeof(double) : sizeof(float);
     const size_t nl1 = (size_t)std::max<int64_t>(NL, 1);
     // footprint check against free device memory
@@ -869,11 +894,12 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
     GC_TRY_HIP(sc.alloc_n(&std_c, (size_t)std::max<int64_t>(n, 1) * P));
     if (n > 0) {
         const int chunk = hyper->chunk_iters > 0 ? hyper->chunk_iters : 1000;
-        const int nck = (n_iter + chunk - 1) / chunk;
+        const int t_first = hyper->t_start;
+        const int nck = (n_iter - t_first + chunk - 1) / chunk;
         jobs.assign(nck, J);
         for (int c = 0; c < nck; ++c) {
-            jobs[c].t0 = c * chunk;
-            jobs[c].t1 = std::min(n_iter, (c + 1) * chunk);
+            jobs[c].t0 = t_first + c * chunk;
+            jobs[c].t1 = std::min(n_iter, t_first + (c + 1) * chunk);
         }
         MhJob* djob = nullptr;
         GC_TRY_HIP(sc.alloc_n(&djob, (size_t)nck));

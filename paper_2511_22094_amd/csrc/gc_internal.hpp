@@ -27,8 +27,11 @@ struct MhJob {
     int P;
     uint32_t k0, k1;         // Philox key = seed
     int t0, t1;              // iterations of this launch
-    int burnin, thin, K;     // retention; K = samples per chain
+    int burnin, thin, K;     // retention; K = samples per chain in this call
+    int k_base;              // samples retained before this call's first step
     int x0_mode;
+    const double* init_state;   // [P][C n] start states (resume) or nullptr
+    const double* init_logl;    // [C][n] their log-likelihoods or nullptr
     float lb[kMaxP], ub[kMaxP], step[kMaxP], x0c[kMaxP];
     double lbd[kMaxP], ubd[kMaxP], stepd[kMaxP], x0cd[kMaxP];
     float inv2s2;

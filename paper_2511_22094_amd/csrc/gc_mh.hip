@@ -70,7 +70,10 @@ __global__ __launch_bounds__(kBlock) void mh_init_kernel(const MhJob* __restrict
     const int64_t v = L % n;
     const int c = (int)(L / n);
     R th[P];
-    if (J.x0_mode == 1) {
+    if (J.init_state) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) th[p] = (R)J.init_state[(int64_t)p * NL + L];
+    } else if (J.x0_mode == 1) {
 #pragma unroll
         for (int b = 0; b < (P + 3) / 4; ++b) {
             U4 o = philox4x32_10(U4{(uint32_t)v, (uint32_t)c | (1u << 16), 0u, (uint32_t)b},
@@ -92,7 +95,9 @@ __global__ __launch_bounds__(kBlock) void mh_init_kernel(const MhJob* __restrict
     }
     const R w = J.w ? (R)J.w[v] : (R)1;
     YGlob y{J.y, n, v, J.acq.M};
-    const R ll = -(inv2s2R<R>(J) * w * w) * Mdl::template sse<0>(th, y, J.acq);
+    // a resumed chain carries its log-likelihood over unchanged (bit for bit)
+    const R ll = J.init_logl ? (R)J.init_logl[L]
+                             : -(inv2s2R<R>(J) * w * w) * Mdl::template sse<0>(th, y, J.acq);
     R* TH = (R*)J.th;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
         acc += a ? 1 : 0;
         if (t == keep_t) {   // uniform across the job
             keep_t += thin;
-            const int k = (t - B + 1) / thin;   // 1-based sample count of this chain
+            const int k = (t - B + 1) / thin - J.k_base;   // 1-based, this call
             const double inv = 1.0 / (double)k;
 #pragma unroll
             for (int p = 0; p < P; ++p) {

@@ -222,3 +222,48 @@ def test_mcmc_rejects_bad_arguments():
     with pytest.raises(g.GcError) as e:
         g.gc_mcmc(m, y, None, lb, ub, 1, 100, 10, 1, sigma=0.1)
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_mh_resume_is_uninterrupted(orc, prec):
+    """A run stopped at step T1 and resumed from its final state continues the
+    same chains bit for bit; samples and accept counts split at T1; the
+    moments of the two calls pool to those of the uninterrupted run."""
+    d = _small("gre3", (3, 6, 5), 31, 0.01)
+    _, yg = _data(orc, d)
+    m = _model(d)
+    g = G()
+    kw = dict(sigma=d.sigma, step=synth.MH_STEP[d.model], seed=9, precision=prec,
+              samples=True, final_state=True)
+    C, T, T1, B, th = 3, 600, 350, 100, 10
+    full = g.gc_mcmc(m, yg, d.mask, d.lb, d.ub, C, T, B, th, **kw)
+    a = g.gc_mcmc(m, yg, d.mask, d.lb, d.ub, C, T1, B, th, **kw)
+    b = g.gc_mcmc(m, yg, d.mask, d.lb, d.ub, C, T, B, th, t_start=T1,
+                  init_state=a["final_state"], init_logl=a["final_logl"], chunk_iters=97, **kw)
+    assert np.array_equal(b["final_state"], full["final_state"])
+    assert np.array_equal(b["final_logl"], full["final_logl"])
+    assert np.array_equal(a["accept"] + b["accept"], full["accept"])
+    assert np.array_equal(np.concatenate([a["samples"], b["samples"]], axis=1), full["samples"])
+    # pooled moments of the two calls (K_a and K_b samples per chain)
+    Ka, Kb = a["samples"].shape[1], b["samples"].shape[1]
+    sel = d.mask.astype(bool)
+    ma, mb = a["mean"][:, sel], b["mean"][:, sel]
+    va, vb = a["std"][:, sel] ** 2, b["std"][:, sel] ** 2
+    na, nb = C * Ka, C * Kb
+    mu = (na * ma + nb * mb) / (na + nb)
+    m2 = (na - 1) * va + (nb - 1) * vb + na * nb / (na + nb) * (ma - mb) ** 2
+    np.testing.assert_allclose(mu, full["mean"][:, sel], rtol=1e-11)
+    np.testing.assert_allclose(np.sqrt(m2 / (na + nb - 1)), full["std"][:, sel], rtol=1e-9)
+
+
+def test_mh_resume_argument_checks():
+    g = G()
+    d = _small("monoexp_t2s", (1, 2, 3), 32, 0.01)
+    y = np.zeros((12, 1, 2, 3), np.float32)
+    m = _model(d)
+    with pytest.raises(g.GcError):      # t_start > 0 without a state
+        g.gc_mcmc(m, y, d.mask, d.lb, d.ub, 1, 100, 10, 2, sigma=0.01, t_start=50)
+    st = np.zeros((2, 1, d.n))
+    with pytest.raises(g.GcError):      # fewer than 2 retained samples left
+        g.gc_mcmc(m, y, d.mask, d.lb, d.ub, 1, 100, 10, 2, sigma=0.01, t_start=98,
+                  init_state=st)
