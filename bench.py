@@ -12,6 +12,10 @@ Second leg (``adam``): the whole-volume Adam fit with 3D TV on the stick +
 ball diffusion workload (64^3 voxels, 96 measurements, 500 iterations,
 lambda 1e-3 on f, Da, De), voxel-iterations per second.
 
+Third leg (``sense``): image reconstruction with the same solver (one slice
+of a 6-echo, 32-coil, 256 x 256 CAIPI R_z = 9 acquisition, L1 loss with 2D
+TV, Adam 500 iterations), iterations per second.
+
 Each leg reports a roofline entry for its dominant kernel: algorithmic
 FLOPs (MH, ALU bound) or bytes (Adam+TV step, HBM bound) per launch divided
 by the launch time measured with HIP events on the launch stream.  The CPU
@@ -160,6 +164,63 @@ def adam_leg(g, torch, steps, warmup):
     gbs = BYTES_PER_ADAM_TV_VOXEL_ITER * n / per_launch_s / 1e9
     return dict(units=units, sec=sec, value=units / sec, per_launch_us=per_launch_s * 1e6,
                 achieved_gbs=gbs, final_loss=r["final_loss"], n=n)
+
+
+def sense_bytes(E, Nc, N, S):
+    """Algorithmic HBM bytes of each reconstruction stage for one iteration
+    (E echoes, Nc coils, N = Ny Nz pixels, S sampled (echo, y, z) entries):
+    every array a stage must read or write, counted once; k-space counts only
+    its sampled entries."""
+    coil_imgs = 8 * E * Nc * N
+    return {
+        "sense_rows_fwd": 8 * E * N + 8 * Nc * N + coil_imgs,
+        "sense_cols": 2 * coil_imgs + 8 * Nc * S + E * N,
+        "sense_rows_adj": 2 * coil_imgs + 8 * Nc * N,
+        "sense_update": coil_imgs + 8 * E * N + 16 * E * N + 24 * E * N,
+    }
+
+
+def sense_leg(g, torch, steps, warmup):
+    from paper_2511_22094_amd import synth
+    kw = synth.SENSE_RECON
+    E, Nc, Ny, Nz = kw["n_echo"], kw["n_coil"], kw["ny"], kw["nz"]
+    d = synth.sense_draw(41, E, Nc, Ny, Nz, sigma=kw["sigma"], noise=False)
+    dev = torch.device("cuda:0")
+    C = torch.from_numpy(d.coils.astype(np.complex64)).to(dev)
+    M = torch.from_numpy(d.mask).to(dev)
+    x = torch.from_numpy(d.truth.astype(np.complex64)).to(dev)
+    gen = torch.Generator(device=dev).manual_seed(42)
+    noise = torch.complex(torch.randn((E, Nc, Ny, Nz), generator=gen, device=dev),
+                          torch.randn((E, Nc, Ny, Nz), generator=gen, device=dev))
+    k = (g.gc_sense_forward(x, C, M) + kw["sigma"] * noise * M[:, None]).contiguous()
+    out = torch.empty((E, Ny, Nz), dtype=torch.complex64, device=dev)
+
+    def run():
+        return g.gc_sense_recon(k, C, M, lr=kw["lr"], n_iter=kw["n_iter"], loss=kw["loss"],
+                                lam=kw["lam"], out=out)
+
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    g.gc_timing_reset()
+    g.gc_timing_enable(True, every=10)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.gc_timing_enable(False)
+    S = int(d.mask.sum())
+    nbytes = sense_bytes(E, Nc, Ny * Nz, S)
+    stages = {}
+    for fam, b in nbytes.items():
+        kms, nl = g.gc_timing_get(fam)
+        us = kms * 1e3 / max(nl, 1)
+        stages[fam] = {"launch_us": us, "bytes": b, "achieved_gbs": b / (us * 1e-6) / 1e9}
+    sec = (t1 - t0) / steps
+    err = float((out - x).abs().pow(2).sum().sqrt() / x.abs().pow(2).sum().sqrt())
+    return dict(sec=sec, iters=kw["n_iter"], value=kw["n_iter"] / sec, stages=stages,
+                final_loss=r["final_loss"], rel_err=err)
 
 
 def copy_leg(torch, mib=256, reps=3):
@@ -355,6 +416,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adam", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-sense", action="store_true")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving leg on the full 256-job trace (voxels up to 1e6)")
     ap.add_argument("--sweep", action="store_true",
@@ -384,6 +446,9 @@ def main():
             elif leg == "adam":
                 r = adam_leg(g, torch, 1, 0)
                 rep[leg] = {"per_launch_us": r["per_launch_us"], "n": r["n"]}
+            elif leg == "sense":
+                r = sense_leg(g, torch, 1, 0)
+                rep[leg] = {k: v["launch_us"] for k, v in r["stages"].items()}
             elif leg == "copy":
                 rep[leg] = copy_leg(torch)
             else:
@@ -400,6 +465,12 @@ def main():
         adam = adam_leg(g, torch, args.steps, args.warmup)
         log(f"bench: Adam {adam['value']:.3e} voxel-iter/s, step kernel "
             f"{adam['per_launch_us']:.1f} us")
+    sense = None
+    if not args.no_sense:
+        log("bench: reconstruction leg (6 echoes x 32 coils, 256 x 256, 500 iterations)")
+        sense = sense_leg(g, torch, args.steps, args.warmup)
+        log(f"bench: reconstruction {sense['value']:.1f} iterations/s, "
+            + ", ".join(f"{k} {v['launch_us']:.1f} us" for k, v in sense["stages"].items()))
     serve = None
     if not args.no_serve:
         serve = serve_leg(g, torch, args.serve_full)
@@ -444,6 +515,21 @@ def main():
                                     "traffic": measured_traffic("fit_step"),
                                     "bytes_per_voxel_iter": BYTES_PER_ADAM_TV_VOXEL_ITER,
                                     "launch_us": adam["per_launch_us"]}}
+    if sense is not None:
+        dom = max(sense["stages"], key=lambda k: sense["stages"][k]["launch_us"])
+        st = sense["stages"][dom]
+        out["sense"] = {"value": sense["value"], "unit": "iterations/s",
+                        "ms_per_step": sense["sec"] * 1e3,
+                        "workload": "SENSE recon, 1 slice: 6 echoes, 32 coils, 256x256, CAIPI "
+                                    "R_z=9, L1 + 2D TV lambda 0.05, Adam 500 iterations",
+                        "rel_err_vs_truth": sense["rel_err"],
+                        "stages_us": {k: v["launch_us"] for k, v in sense["stages"].items()},
+                        "roofline": {"bound": "hbm", "kernel": dom,
+                                     "achieved": st["achieved_gbs"], "peak": PEAK_HBM_GBS,
+                                     "unit": "GB/s", "frac": st["achieved_gbs"] / PEAK_HBM_GBS,
+                                     "traffic": measured_traffic(dom),
+                                     "bytes_per_launch": st["bytes"],
+                                     "launch_us": st["launch_us"]}}
     if serve is not None:
         out["serving"] = serve
     print(json.dumps(out))

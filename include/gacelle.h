@@ -301,6 +301,48 @@ int gc_tv_graph(int64_t n, const int64_t *rowptr, const int32_t *col, int64_t nn
                 const float *u, double scale, double *R, float *dR, const gc_exec *exec);
 
 /* ------------------------------------------------------------------------
+ * Image reconstruction with the askadam solver (paper §2.6.4, Eq. 7):
+ * multi-coil, multi-echo SENSE-type reconstruction of one slice after the
+ * read-out transform.  With k_ec the measured samples of echo e and coil c,
+ * C_c the coil sensitivities, M_e the sampling mask and F2 the unitary 2D
+ * DFT over (y, z) (exponent -2 pi i), the solver minimises over the complex
+ * image I [E][Ny][Nz]
+ *   L(I) = 1/Nk sum_{e,c,(y,z) in M_e} l(F2(C_c I_e) - k_ec)
+ *        + lambda/Npix sum_e TV2(Re I_e) + TV2(Im I_e)
+ * with l = |Re r|^2 + |Im r|^2 (loss 2) or |Re r| + |Im r| (loss 1),
+ * Nk = 2 Nc (number of sampled entries over all echoes), Npix = E Ny Nz and
+ * TV2 the anisotropic sum of |forward differences| along y and z.  The
+ * optimiser (gc_adam_hyper: optimizer, lr in image units, betas, eps,
+ * momentum, rho, n_iter, loss, lambda, tol, conv_value, conv_window,
+ * loss_history) updates Re I and Im I without bounds, from `init` or 0.
+ * Complex arrays are interleaved (re, im) floats.  Ny and Nz are powers of
+ * two, 2 <= Ny <= 1024, 16 <= Nz <= 1024, and 1 <= n_echo, n_coil <= 1024
+ * (GC_E_INVAL otherwise; also for a reconstruction whose mask samples
+ * nothing).  Working memory: about 8 E Nc Ny Nz + 32 E Ny Nz bytes of device
+ * memory per call, released before return.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int ny, nz, n_echo, n_coil;
+    const float *kspace;   /* [E][Nc][Ny][Nz] complex, exec memory; entries
+                              outside the mask are ignored (NULL for the
+                              operator entry points) */
+    const float *coils;    /* [Nc][Ny][Nz] complex, exec memory */
+    const uint8_t *mask;   /* [E][Ny][Nz] 1 = sampled, exec memory */
+    const float *init;     /* [E][Ny][Nz] complex start image or NULL = 0 */
+} gc_sense_problem;
+
+/* Reconstruction; out_image [E][Ny][Nz] complex (exec memory). */
+int gc_sense_recon(const gc_sense_problem *prob, const gc_adam_hyper *hyper, float *out_image,
+                   gc_fit_report *report, const gc_exec *exec);
+/* The operator and its adjoint (autograd building blocks):
+ * out [E][Nc][Ny][Nz] = M_e F2(C_c I_e) (zero outside the mask);
+ * out [E][Ny][Nz] = sum_c conj(C_c) F2^H(M_e r_ec). */
+int gc_sense_forward(const gc_sense_problem *prob, const float *image, float *out,
+                     const gc_exec *exec);
+int gc_sense_adjoint(const gc_sense_problem *prob, const float *kspace, float *out,
+                     const gc_exec *exec);
+
+/* ------------------------------------------------------------------------
  * Counter-based random stream (for bit-exact tests against the oracle).
  * ------------------------------------------------------------------------ */
 /* out[n][4] = Philox4x32-10(ctr[n][4], key = (seed lo, seed hi)) */
@@ -316,7 +358,8 @@ int gc_philox_uniform_normal(uint64_t seed, const uint32_t *ctr, int64_t n, int 
  * Kernel timing (profiling aid).  While enabled, launches of a hot kernel
  * family are bracketed by HIP events recorded on the stream they run on;
  * totals accumulate per family: "mh_chunk", "ens_chunk", "fit_fused",
- * "fit_step".  on = 0 disables (the default); on = k > 0 times every k-th
+ * "fit_step", and the four reconstruction stages "sense_rows_fwd",
+ * "sense_cols", "sense_rows_adj", "sense_update".  on = 0 disables (the default); on = k > 0 times every k-th
  * launch of a family within one call (k = 1: every launch), which bounds
  * the cost of the two event records per timed launch for families launched
  * once per iteration.  The count returned by gc_timing_get is that of the

@@ -97,6 +97,11 @@ class gc_mcmc_hyper(ctypes.Structure):
                 ("init_state", c_void_p), ("init_logl", c_void_p)]
 
 
+class gc_sense_problem(ctypes.Structure):
+    _fields_ = [("ny", c_int), ("nz", c_int), ("n_echo", c_int), ("n_coil", c_int),
+                ("kspace", c_void_p), ("coils", c_void_p), ("mask", c_void_p), ("init", c_void_p)]
+
+
 class gc_server_cfg(ctypes.Structure):
     _fields_ = [("device", c_int), ("hbm_budget", c_size_t), ("max_slots", c_int),
                 ("chunk_iters", c_int), ("baseline", c_int)]
@@ -144,6 +149,10 @@ _sig = {
                    ctypes.POINTER(gc_exec)], c_int),
     "gc_tv_graph": ([c_int64, P, P, c_int64, P, c_double, ctypes.POINTER(c_double), P,
                      ctypes.POINTER(gc_exec)], c_int),
+    "gc_sense_recon": ([ctypes.POINTER(gc_sense_problem), ctypes.POINTER(gc_adam_hyper), P,
+                        ctypes.POINTER(gc_fit_report), ctypes.POINTER(gc_exec)], c_int),
+    "gc_sense_forward": ([ctypes.POINTER(gc_sense_problem), P, P, ctypes.POINTER(gc_exec)], c_int),
+    "gc_sense_adjoint": ([ctypes.POINTER(gc_sense_problem), P, P, ctypes.POINTER(gc_exec)], c_int),
     "gc_philox": ([c_uint64, P, c_int64, P, ctypes.POINTER(gc_exec)], c_int),
     "gc_philox_uniform_normal": ([c_uint64, P, c_int64, c_int, P, P, ctypes.POINTER(gc_exec)], c_int),
     "gc_timing_enable": ([c_int], c_int),
@@ -537,6 +546,107 @@ def _host(x, dt, keep):
     arr = np.ascontiguousarray(x, dtype=dt)
     keep.append(arr)
     return arr.ctypes.data
+
+
+# ------------------------------------------------------------ reconstruction
+def _cplx_in(a, args: _Args):
+    """Complex array -> pointer to interleaved float32 (numpy complex64/128 or a
+    torch complex64 tensor on the GPU)."""
+    if a is None:
+        return None
+    if _is_torch(a):
+        import torch
+        if a.dtype != torch.complex64:
+            raise TypeError(f"expected torch.complex64, got {a.dtype}")
+        return args.ptr(torch.view_as_real(a.contiguous()), np.float32)
+    return args.ptr(np.ascontiguousarray(a, np.complex64).view(np.float32), np.float32)
+
+
+def _cplx_out(args: _Args, shape, like, out):
+    if out is None:
+        if _is_torch(like):
+            import torch
+            out = torch.empty(shape, dtype=torch.complex64, device=like.device)
+        else:
+            out = np.empty(shape, np.complex64)
+    if _is_torch(out):
+        import torch
+        if out.dtype != torch.complex64 or not out.is_contiguous():
+            raise TypeError("output must be a contiguous torch.complex64 tensor")
+        return out, args.out(torch.view_as_real(out), np.float32)
+    if out.dtype != np.complex64 or not out.flags.c_contiguous:
+        raise TypeError("output must be a contiguous complex64 array")
+    return out, args.out(out.view(np.float32), np.float32)
+
+
+def _sense_problem(coils, mask, kspace, init, args: _Args):
+    Nc, Ny, Nz = (int(d) for d in coils.shape)
+    E = int(mask.shape[0])
+    if tuple(mask.shape) != (E, Ny, Nz):
+        raise ValueError(f"mask must be [E, {Ny}, {Nz}], got {tuple(mask.shape)}")
+    if kspace is not None and tuple(kspace.shape) != (E, Nc, Ny, Nz):
+        raise ValueError(f"kspace must be {(E, Nc, Ny, Nz)}, got {tuple(kspace.shape)}")
+    if init is not None and tuple(init.shape) != (E, Ny, Nz):
+        raise ValueError(f"init must be {(E, Ny, Nz)}, got {tuple(init.shape)}")
+    pr = gc_sense_problem(Ny, Nz, E, Nc)
+    pr.kspace = _cplx_in(kspace, args)
+    pr.coils = _cplx_in(coils, args)
+    pr.mask = args.ptr(mask, np.uint8)
+    pr.init = _cplx_in(init, args)
+    return pr, (E, Nc, Ny, Nz)
+
+
+def gc_sense_recon(kspace, coils, mask, *, init=None, optimizer="adam", lr=0.01, beta1=0.9,
+                   beta2=0.999, eps=1e-8, momentum=0.9, rho=0.9, n_iter=100, loss=2, lam=0.0,
+                   tol=0.0, conv_value=0.0, conv_window=20, loss_history=False, out=None):
+    """kspace [E, Nc, Ny, Nz], coils [Nc, Ny, Nz] complex, mask [E, Ny, Nz] uint8 ->
+    dict(image [E, Ny, Nz] complex64, iters_run, final_loss, stop_reason[, loss])."""
+    a = _Args()
+    pr, (E, Nc, Ny, Nz) = _sense_problem(coils, mask, kspace, init, a)
+    h = gc_adam_hyper()
+    _L.gc_adam_defaults(ctypes.byref(h))
+    h.optimizer = OPTIMIZERS[optimizer]
+    h.lr, h.beta1, h.beta2, h.eps, h.momentum, h.rho = lr, beta1, beta2, eps, momentum, rho
+    h.n_iter, h.loss, h.lambda_ = n_iter, loss, lam
+    h.tol, h.conv_value, h.conv_window = tol, conv_value, conv_window
+    hist = np.zeros(max(n_iter, 1)) if loss_history else None
+    h.loss_history = None if hist is None else hist.ctypes.data
+    img, op = _cplx_out(a, (E, Ny, Nz), kspace, out)
+    rep = gc_fit_report()
+    ex = a.exec()
+    _check(_L.gc_sense_recon(ctypes.byref(pr), ctypes.byref(h), op, ctypes.byref(rep),
+                             ctypes.byref(ex)))
+    r = dict(image=img, iters_run=rep.iters_run, final_loss=rep.final_loss,
+             stop_reason=rep.stop_reason)
+    if hist is not None:
+        r["loss"] = hist[: rep.iters_run]
+    return r
+
+
+def gc_sense_forward(image, coils, mask, out=None):
+    """[E, Ny, Nz] -> [E, Nc, Ny, Nz] = M_e F2(C_c I_e), complex64."""
+    a = _Args()
+    pr, (E, Nc, Ny, Nz) = _sense_problem(coils, mask, None, None, a)
+    if tuple(image.shape) != (E, Ny, Nz):
+        raise ValueError(f"image must be {(E, Ny, Nz)}")
+    ip = _cplx_in(image, a)
+    res, op = _cplx_out(a, (E, Nc, Ny, Nz), image, out)
+    ex = a.exec()
+    _check(_L.gc_sense_forward(ctypes.byref(pr), ip, op, ctypes.byref(ex)))
+    return res
+
+
+def gc_sense_adjoint(kspace, coils, mask, out=None):
+    """[E, Nc, Ny, Nz] -> [E, Ny, Nz] = sum_c conj(C_c) F2^H(M_e r_ec), complex64."""
+    a = _Args()
+    pr, (E, Nc, Ny, Nz) = _sense_problem(coils, mask, None, None, a)
+    if tuple(kspace.shape) != (E, Nc, Ny, Nz):
+        raise ValueError(f"kspace must be {(E, Nc, Ny, Nz)}")
+    kp = _cplx_in(kspace, a)
+    res, op = _cplx_out(a, (E, Ny, Nz), kspace, out)
+    ex = a.exec()
+    _check(_L.gc_sense_adjoint(ctypes.byref(pr), kp, op, ctypes.byref(ex)))
+    return res
 
 
 def gc_philox(seed: int, ctr):

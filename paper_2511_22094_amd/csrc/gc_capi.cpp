@@ -1202,3 +1202,246 @@ int gc_philox_uniform_normal(uint64_t seed, const uint32_t* ctr, int64_t n, int 
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ reconstruction
+namespace {
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+int ilog2(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+// Validates the problem, stages its arrays and builds the kernel descriptor.
+int sense_setup(Scratch& sc, const gc_sense_problem* pr, int mem_kind, bool need_k, SenseDev* S,
+                int64_t* n_sampled) {
+    GC_REQUIRE(pr, GC_E_INVAL, "problem missing");
+    GC_REQUIRE(pow2_in(pr->ny, 2, kSenseMaxN) && pow2_in(pr->nz, kSenseCols, kSenseMaxN),
+               GC_E_INVAL, "ny must be a power of two in 2..%d, nz in %d..%d", kSenseMaxN,
+               kSenseCols, kSenseMaxN);
+    GC_REQUIRE(pr->n_echo >= 1 && pr->n_echo <= 1024 && pr->n_coil >= 1 && pr->n_coil <= 1024 &&
+                   pr->coils && pr->mask,
+               GC_E_INVAL, "need 1 <= n_echo, n_coil <= 1024, coils and mask");
+    GC_REQUIRE(!need_k || pr->kspace, GC_E_INVAL, "kspace missing");
+    const int E = pr->n_echo, Nc = pr->n_coil, Ny = pr->ny, Nz = pr->nz;
+    const size_t pix = (size_t)Ny * Nz;
+    const hipStream_t s = sc.s;
+    const void *dc, *dm, *dk = nullptr;
+    int rc;
+    if ((rc = stage_in(sc, pr->coils, (size_t)Nc * pix * 8, mem_kind, &dc))) return rc;
+    if ((rc = stage_in(sc, pr->mask, (size_t)E * pix, mem_kind, &dm))) return rc;
+    if (need_k && (rc = stage_in(sc, pr->kspace, (size_t)E * Nc * pix * 8, mem_kind, &dk)))
+        return rc;
+    // sampled entries: the mask is small, count it on the host
+    std::vector<uint8_t> hm((size_t)E * pix);
+    GC_TRY_HIP(hipMemcpyAsync(hm.data(), dm, hm.size(), hipMemcpyDeviceToHost, s));
+    // twiddles exp(-2 pi i k / N), FP64 then rounded once
+    std::vector<float> tw((size_t)(Ny / 2 + Nz / 2) * 2);
+    for (int k = 0; k < Ny / 2; ++k) {
+        const double a = -2.0 * M_PI * k / Ny;
+        tw[2 * k] = (float)std::cos(a);
+        tw[2 * k + 1] = (float)std::sin(a);
+    }
+    for (int k = 0; k < Nz / 2; ++k) {
+        const double a = -2.0 * M_PI * k / Nz;
+        tw[Ny + 2 * k] = (float)std::cos(a);
+        tw[Ny + 2 * k + 1] = (float)std::sin(a);
+    }
+    float* dtw = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&dtw, tw.size()));
+    GC_TRY_HIP(hipMemcpyAsync(dtw, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    int64_t cnt = 0;
+    for (uint8_t b : hm) cnt += b ? 1 : 0;
+    *n_sampled = cnt;
+    SenseDev& D = *S;
+    D = SenseDev{};
+    D.E = E;
+    D.Nc = Nc;
+    D.Ny = Ny;
+    D.Nz = Nz;
+    D.logNy = ilog2(Ny);
+    D.logNz = ilog2(Nz);
+    D.G = std::min(kSenseCols, kSenseColElems / Ny);
+    D.rsqrtNy = (float)(1.0 / std::sqrt((double)Ny));
+    D.rsqrtNz = (float)(1.0 / std::sqrt((double)Nz));
+    D.coils = (const float2*)dc;
+    D.ksp = (const float2*)dk;
+    D.mask = (const uint8_t*)dm;
+    D.twy = (const float2*)dtw;
+    D.twz = (const float2*)(dtw + Ny);
+    D.scale_data = cnt > 0 ? (float)(1.0 / (2.0 * Nc * (double)cnt)) : 0.f;
+    return GC_OK;
+}
+
+}  // namespace
+
+int gc_sense_recon(const gc_sense_problem* pr, const gc_adam_hyper* h, float* out_image,
+                   gc_fit_report* report, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    int rc;
+    GC_REQUIRE(h && out_image, GC_E_INVAL, "null hyper or output");
+    GC_REQUIRE(h->n_iter >= 1 && (h->loss == 1 || h->loss == 2) && h->optimizer >= 0 &&
+                   h->optimizer <= 2 && h->lr > 0 && std::isfinite(h->lr) && h->lambda >= 0 &&
+                   h->beta1 >= 0 && h->beta1 < 1 && h->beta2 >= 0 && h->beta2 < 1 &&
+                   h->eps >= 0 && h->rho >= 0 && h->rho < 1 && h->momentum >= 0,
+               GC_E_INVAL, "bad optimiser hyper-parameters");
+    GC_REQUIRE(!(h->conv_value > 0) || h->conv_window > 1, GC_E_INVAL, "conv_window must be > 1");
+    DeviceScope ds;
+    if ((rc = ds.open(exec))) return rc;
+    const hipStream_t s = ds.stream;
+    Scratch sc(s);
+    SenseDev S;
+    int64_t nsamp = 0;
+    if ((rc = sense_setup(sc, pr, ds.mem_kind, true, &S, &nsamp))) return rc;
+    GC_REQUIRE(nsamp > 0, GC_E_INVAL, "the mask samples nothing");
+    const int T = h->n_iter;
+    const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
+    const size_t nbuf = (size_t)S.E * S.Nc * S.Ny * S.Nz;
+    float2 *img0 = nullptr, *img1 = nullptr, *m = nullptr, *v = nullptr, *buf = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&img0, (size_t)npix));
+    GC_TRY_HIP(sc.alloc_n(&img1, (size_t)npix));
+    GC_TRY_HIP(sc.alloc_n(&m, (size_t)npix));
+    GC_TRY_HIP(sc.alloc_n(&v, (size_t)npix));
+    GC_TRY_HIP(sc.alloc_n(&buf, nbuf));
+    GC_TRY_HIP(fill_f32((float*)m, npix * 2, 0.f, s));
+    GC_TRY_HIP(fill_f32((float*)v, npix * 2, 0.f, s));
+    if (pr->init) {
+        const void* di;
+        if ((rc = stage_in(sc, pr->init, (size_t)npix * 8, ds.mem_kind, &di))) return rc;
+        GC_TRY_HIP(hipMemcpyAsync(img0, di, (size_t)npix * 8, hipMemcpyDeviceToDevice, s));
+    } else {
+        GC_TRY_HIP(fill_f32((float*)img0, npix * 2, 0.f, s));
+    }
+    const int64_t nparts = sense_partials(S);
+    float* partial = nullptr;
+    double* hist = nullptr;
+    int* stop = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&partial, (size_t)nparts));
+    GC_TRY_HIP(sc.alloc_n(&hist, (size_t)T));
+    GC_TRY_HIP(sc.alloc_n(&stop, 2));
+    GC_TRY_HIP(fill_i32(stop, 2, 0, s));
+    S.loss_p = h->loss;
+    SenseOpt O{};
+    O.optimizer = h->optimizer;
+    O.lr = (float)h->lr;
+    O.beta1 = (float)h->beta1;
+    O.beta2 = (float)h->beta2;
+    O.eps = (float)h->eps;
+    O.momentum = (float)h->momentum;
+    O.rho = (float)h->rho;
+    O.omb1 = (float)(1.0 - h->beta1);
+    O.omb2 = (float)(1.0 - h->beta2);
+    O.omrho = (float)(1.0 - h->rho);
+    O.scale_tv = (float)(h->lambda / (double)npix);
+    const bool stopping = h->tol > 0 || h->conv_value > 0;
+    const bool each = stopping || h->loss_history != nullptr;
+    const double tol = h->tol > 0 ? h->tol : -INFINITY;
+    double b1 = 1.0, b2 = 1.0;
+    int hstop[2] = {0, 0};
+    LaunchTimer tm[kSenseStages] = {{"sense_rows_fwd", s}, {"sense_cols", s},
+                                     {"sense_rows_adj", s}, {"sense_update", s}};
+    for (int t = 1; t <= T; ++t) {
+        b1 *= h->beta1;
+        b2 *= h->beta2;
+        O.c1 = (float)(1.0 / (1.0 - b1));
+        O.c2 = (float)(1.0 / (1.0 - b2));
+        const bool rec = each || t == T;
+        const float2* in = (t % 2 == 1) ? img0 : img1;
+        float2* out = (t % 2 == 1) ? img1 : img0;
+        for (int k = 0; k < kSenseStages; ++k) {
+            tm[k].begin();
+            GC_TRY_HIP(sense_stage(k, S, O, in, out, m, v, buf, rec ? partial : nullptr,
+                                   stopping ? stop : nullptr, s));
+            tm[k].end();
+        }
+        if (rec)
+            GC_TRY_HIP(fit_loss_stop(partial, nparts, hist, t, tol, h->conv_value, h->conv_window,
+                                     stop, s));
+        if (stopping && t % 32 == 0 && t < T) {
+            GC_TRY_HIP(hipMemcpyAsync(hstop, stop, sizeof(hstop), hipMemcpyDeviceToHost, s));
+            GC_TRY_HIP(hipStreamSynchronize(s));
+            if (hstop[0] != 0) break;
+        }
+    }
+    GC_TRY_HIP(hipMemcpyAsync(hstop, stop, sizeof(hstop), hipMemcpyDeviceToHost, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    for (auto& x : tm) x.flush();
+    const int iters = hstop[0] != 0 ? hstop[0] : T;
+    double final_loss = 0.0;
+    GC_TRY_HIP(hipMemcpyAsync(&final_loss, hist + (iters - 1), sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    if (h->loss_history)
+        GC_TRY_HIP(hipMemcpyAsync(h->loss_history, hist, (size_t)iters * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+    const float2* fin = (iters % 2 == 1) ? img1 : img0;
+    GC_TRY_HIP(hipMemcpyAsync(out_image, fin, (size_t)npix * 8,
+                              ds.mem_kind == GC_MEM_HOST ? hipMemcpyDeviceToHost
+                                                         : hipMemcpyDeviceToDevice, s));
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    if (report) {
+        report->iters_run = iters;
+        report->final_loss = final_loss;
+        report->stop_reason = hstop[0] != 0 ? hstop[1] : 0;
+    }
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_sense_forward(const gc_sense_problem* pr, const float* image, float* out,
+                     const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    int rc;
+    GC_REQUIRE(image && out, GC_E_INVAL, "null image or output");
+    DeviceScope ds;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    SenseDev S;
+    int64_t nsamp = 0;
+    if ((rc = sense_setup(sc, pr, ds.mem_kind, false, &S, &nsamp))) return rc;
+    const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
+    const size_t nbuf = (size_t)S.E * S.Nc * S.Ny * S.Nz;
+    const void* di;
+    if ((rc = stage_in(sc, image, (size_t)npix * 8, ds.mem_kind, &di))) return rc;
+    float2* dout = (float2*)out;
+    if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dout, nbuf));
+    GC_TRY_HIP(sense_forward_op(S, (const float2*)di, dout, ds.stream));
+    if (ds.mem_kind == GC_MEM_HOST)
+        GC_TRY_HIP(hipMemcpyAsync(out, dout, nbuf * 8, hipMemcpyDeviceToHost, ds.stream));
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
+
+int gc_sense_adjoint(const gc_sense_problem* pr, const float* kspace, float* out,
+                     const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    int rc;
+    GC_REQUIRE(kspace && out, GC_E_INVAL, "null input or output");
+    DeviceScope ds;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    SenseDev S;
+    int64_t nsamp = 0;
+    if ((rc = sense_setup(sc, pr, ds.mem_kind, false, &S, &nsamp))) return rc;
+    const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
+    const size_t nbuf = (size_t)S.E * S.Nc * S.Ny * S.Nz;
+    // the adjoint works in place on a copy of the input
+    float2* buf = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&buf, nbuf));
+    GC_TRY_HIP(hipMemcpyAsync(buf, kspace, nbuf * 8,
+                              ds.mem_kind == GC_MEM_HOST ? hipMemcpyHostToDevice
+                                                         : hipMemcpyDeviceToDevice, ds.stream));
+    float2* dout = (float2*)out;
+    if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dout, (size_t)npix));
+    GC_TRY_HIP(sense_adjoint_op(S, buf, dout, ds.stream));
+    if (ds.mem_kind == GC_MEM_HOST)
+        GC_TRY_HIP(hipMemcpyAsync(out, dout, (size_t)npix * 8, hipMemcpyDeviceToHost, ds.stream));
+    GC_TRY_HIP(hipStreamSynchronize(ds.stream));
+    return GC_OK;
+    GC_GUARD_END
+}
