@@ -58,7 +58,16 @@ PEAK_HBM_GBS = 8000.0
 # 256 MiB device copy in the same run gives (bytes it reads / its FETCH_SIZE),
 # WRITE_SIZE likewise.  A figure holds only for the kernel sources it was
 # taken on: when their sha256 differs, `traffic` is reported as null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "mh_chunk": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
+        "sha256": "cb3ef0774db47aac89dc427d69869cdcf1e5bca3add770ee70b63e70902f1329",
+        "read_bytes": 1595948528, "write_bytes": 788529152,
+        "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
+    "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
+        "sha256": "1db4d4b6b8934f476cd244f9e1ba25adccfb9c44a8389ee9aaad04ca1fc362ce",
+        "read_bytes": 126873332, "write_bytes": 15728648,
+        "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
+}
 
 
 def measured_traffic(key):

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "gc_runtime.hpp"
+#include "gc_sense.hpp"
 #include "gc_timing.hpp"
 
 namespace gc {

@@ -13,7 +13,7 @@
 //   update     sum over coils + TV subgradient, optimiser step on Re and Im
 // Sizes along y and z are powers of two up to kSenseMaxN (z at least
 // kSenseCols); the y pass works on tiles of Ny x G columns, G = min(16, 4096/Ny).
-#include "gc_internal.hpp"
+#include "gc_sense.hpp"
 
 namespace gc {
 
