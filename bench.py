@@ -175,17 +175,20 @@ def adam_leg(g, torch, steps, warmup):
                 achieved_gbs=gbs, final_loss=r["final_loss"], n=n)
 
 
-def sense_bytes(E, Nc, N, S):
+def sense_bytes(E, Nc, Ny, Nz, S):
     """Algorithmic HBM bytes of each reconstruction stage for one iteration
     (E echoes, Nc coils, N = Ny Nz pixels, S sampled (echo, y, z) entries):
-    every array a stage must read or write, counted once; k-space counts only
-    its sampled entries."""
+    every array a stage must read or write, counted once; the measured
+    samples count only the sampled entries, the mask one 4-byte word per row
+    of each tile of G = min(16, 4096 / Ny) columns."""
+    N = Ny * Nz
+    G = min(16, 4096 // Ny)
     coil_imgs = 8 * E * Nc * N
     return {
-        "sense_rows_fwd": 8 * E * N + 8 * Nc * N + coil_imgs,
-        "sense_cols": 2 * coil_imgs + 8 * Nc * S + E * N,
-        "sense_rows_adj": 2 * coil_imgs + 8 * Nc * N,
-        "sense_update": coil_imgs + 8 * E * N + 16 * E * N + 24 * E * N,
+        # y pass: coil images in and out, samples, tile row masks
+        "sense_ycols": 2 * coil_imgs + 8 * Nc * S + 4 * E * Ny * (Nz // G),
+        # z pass: coil images in and out, coil maps, image in and out, Adam m, v in and out
+        "sense_zrows": 2 * coil_imgs + 8 * Nc * N + 16 * E * N + 32 * E * N,
     }
 
 
@@ -220,7 +223,7 @@ def sense_leg(g, torch, steps, warmup):
     t1 = time.perf_counter()
     g.gc_timing_enable(False)
     S = int(d.mask.sum())
-    nbytes = sense_bytes(E, Nc, Ny * Nz, S)
+    nbytes = sense_bytes(E, Nc, Ny, Nz, S)
     stages = {}
     for fam, b in nbytes.items():
         kms, nl = g.gc_timing_get(fam)

@@ -358,8 +358,8 @@ int gc_philox_uniform_normal(uint64_t seed, const uint32_t *ctr, int64_t n, int 
  * Kernel timing (profiling aid).  While enabled, launches of a hot kernel
  * family are bracketed by HIP events recorded on the stream they run on;
  * totals accumulate per family: "mh_chunk", "ens_chunk", "fit_fused",
- * "fit_step", and the four reconstruction stages "sense_rows_fwd",
- * "sense_cols", "sense_rows_adj", "sense_update".  on = 0 disables (the default); on = k > 0 times every k-th
+ * "fit_step", and the two reconstruction passes "sense_ycols" and
+ * "sense_zrows".  on = 0 disables (the default); on = k > 0 times every k-th
  * launch of a family within one call (k = 1: every launch), which bounds
  * the cost of the two event records per timed launch for families launched
  * once per iteration.  The count returned by gc_timing_get is that of the

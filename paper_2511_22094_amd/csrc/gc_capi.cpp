@@ -1214,13 +1214,14 @@ int ilog2(int n) {
     return l;
 }
 
-// Validates the problem, stages its arrays and builds the kernel descriptor.
-int sense_setup(Scratch& sc, const gc_sense_problem* pr, int mem_kind, bool need_k, SenseDev* S,
-                int64_t* n_sampled) {
+// Validates the problem, stages its arrays, builds the mask bit words and
+// sample offsets and the twiddle tables, and (need_k) packs the measured
+// samples; fills the kernel descriptor.
+int sense_setup(Scratch& sc, const gc_sense_problem* pr, int mem_kind, bool need_k, SenseDev* S) {
     GC_REQUIRE(pr, GC_E_INVAL, "problem missing");
-    GC_REQUIRE(pow2_in(pr->ny, 2, kSenseMaxN) && pow2_in(pr->nz, kSenseCols, kSenseMaxN),
+    GC_REQUIRE(pow2_in(pr->ny, 2, kSenseMaxN) && pow2_in(pr->nz, kSenseMinNz, kSenseMaxN),
                GC_E_INVAL, "ny must be a power of two in 2..%d, nz in %d..%d", kSenseMaxN,
-               kSenseCols, kSenseMaxN);
+               kSenseMinNz, kSenseMaxN);
     GC_REQUIRE(pr->n_echo >= 1 && pr->n_echo <= 1024 && pr->n_coil >= 1 && pr->n_coil <= 1024 &&
                    pr->coils && pr->mask,
                GC_E_INVAL, "need 1 <= n_echo, n_coil <= 1024, coils and mask");
@@ -1228,51 +1229,82 @@ int sense_setup(Scratch& sc, const gc_sense_problem* pr, int mem_kind, bool need
     const int E = pr->n_echo, Nc = pr->n_coil, Ny = pr->ny, Nz = pr->nz;
     const size_t pix = (size_t)Ny * Nz;
     const hipStream_t s = sc.s;
-    const void *dc, *dm, *dk = nullptr;
+    const void *dc, *dm;
     int rc;
     if ((rc = stage_in(sc, pr->coils, (size_t)Nc * pix * 8, mem_kind, &dc))) return rc;
     if ((rc = stage_in(sc, pr->mask, (size_t)E * pix, mem_kind, &dm))) return rc;
-    if (need_k && (rc = stage_in(sc, pr->kspace, (size_t)E * Nc * pix * 8, mem_kind, &dk)))
-        return rc;
-    // sampled entries: the mask is small, count it on the host
+    // the mask is small: per-tile row masks and sample offsets on the host
     std::vector<uint8_t> hm((size_t)E * pix);
     GC_TRY_HIP(hipMemcpyAsync(hm.data(), dm, hm.size(), hipMemcpyDeviceToHost, s));
-    // twiddles exp(-2 pi i k / N), FP64 then rounded once
-    std::vector<float> tw((size_t)(Ny / 2 + Nz / 2) * 2);
-    for (int k = 0; k < Ny / 2; ++k) {
+    GC_TRY_HIP(hipStreamSynchronize(s));
+    const int logNy = ilog2(Ny), G = sense_tile_cols(logNy), nzg = Nz / G;
+    std::vector<uint32_t> tinfo((size_t)E * nzg * Ny, 0u);
+    std::vector<int32_t> tbase((size_t)E * nzg, 0);
+    int64_t cnt = 0;
+    for (int e = 0; e < E; ++e) {
+        for (int zg = 0; zg < nzg; ++zg) {
+            GC_REQUIRE(cnt < INT32_MAX - 4096, GC_E_INVAL, "too many sampled entries");
+            tbase[(size_t)e * nzg + zg] = (int32_t)cnt;
+            uint32_t local = 0;
+            for (int y = 0; y < Ny; ++y) {
+                uint32_t m16 = 0;
+                for (int j = 0; j < G; ++j)
+                    if (hm[((size_t)e * Ny + y) * Nz + (size_t)zg * G + j]) m16 |= 1u << j;
+                tinfo[((size_t)e * nzg + zg) * Ny + y] = (local << 16) | m16;
+                local += (uint32_t)__builtin_popcount(m16);
+            }
+            cnt += local;
+        }
+    }
+    // twiddles exp(-2 pi i k / N), k < N, in FP64 then rounded once
+    std::vector<float> tw((size_t)(Ny + Nz) * 2);
+    for (int k = 0; k < Ny; ++k) {
         const double a = -2.0 * M_PI * k / Ny;
         tw[2 * k] = (float)std::cos(a);
         tw[2 * k + 1] = (float)std::sin(a);
     }
-    for (int k = 0; k < Nz / 2; ++k) {
+    for (int k = 0; k < Nz; ++k) {
         const double a = -2.0 * M_PI * k / Nz;
-        tw[Ny + 2 * k] = (float)std::cos(a);
-        tw[Ny + 2 * k + 1] = (float)std::sin(a);
+        tw[2 * (Ny + k)] = (float)std::cos(a);
+        tw[2 * (Ny + k) + 1] = (float)std::sin(a);
     }
     float* dtw = nullptr;
+    uint32_t* dti = nullptr;
+    int32_t* dtb = nullptr;
     GC_TRY_HIP(sc.alloc_n(&dtw, tw.size()));
+    GC_TRY_HIP(sc.alloc_n(&dti, tinfo.size()));
+    GC_TRY_HIP(sc.alloc_n(&dtb, tbase.size()));
     GC_TRY_HIP(hipMemcpyAsync(dtw, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    GC_TRY_HIP(hipStreamSynchronize(s));
-    int64_t cnt = 0;
-    for (uint8_t b : hm) cnt += b ? 1 : 0;
-    *n_sampled = cnt;
+    GC_TRY_HIP(hipMemcpyAsync(dti, tinfo.data(), tinfo.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, s));
+    GC_TRY_HIP(hipMemcpyAsync(dtb, tbase.data(), tbase.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
     SenseDev& D = *S;
     D = SenseDev{};
     D.E = E;
     D.Nc = Nc;
     D.Ny = Ny;
     D.Nz = Nz;
-    D.logNy = ilog2(Ny);
+    D.logNy = logNy;
     D.logNz = ilog2(Nz);
-    D.G = std::min(kSenseCols, kSenseColElems / Ny);
+    D.G = G;
+    D.S = cnt;
     D.rsqrtNy = (float)(1.0 / std::sqrt((double)Ny));
     D.rsqrtNz = (float)(1.0 / std::sqrt((double)Nz));
     D.coils = (const float2*)dc;
-    D.ksp = (const float2*)dk;
-    D.mask = (const uint8_t*)dm;
+    D.tinfo = dti;
+    D.tbase = dtb;
     D.twy = (const float2*)dtw;
-    D.twz = (const float2*)(dtw + Ny);
+    D.twz = (const float2*)(dtw + 2 * Ny);
     D.scale_data = cnt > 0 ? (float)(1.0 / (2.0 * Nc * (double)cnt)) : 0.f;
+    if (need_k && cnt > 0) {
+        const void* dk;
+        if ((rc = stage_in(sc, pr->kspace, (size_t)E * Nc * pix * 8, mem_kind, &dk))) return rc;
+        float2* kc = nullptr;
+        GC_TRY_HIP(sc.alloc_n(&kc, (size_t)Nc * cnt));
+        GC_TRY_HIP(sense_pack_kspace(D, (const float2*)dk, kc, s));
+        D.kc = kc;
+    }
     return GC_OK;
 }
 
@@ -1295,9 +1327,9 @@ int gc_sense_recon(const gc_sense_problem* pr, const gc_adam_hyper* h, float* ou
     const hipStream_t s = ds.stream;
     Scratch sc(s);
     SenseDev S;
-    int64_t nsamp = 0;
-    if ((rc = sense_setup(sc, pr, ds.mem_kind, true, &S, &nsamp))) return rc;
-    GC_REQUIRE(nsamp > 0, GC_E_INVAL, "the mask samples nothing");
+    if ((rc = sense_setup(sc, pr, ds.mem_kind, true, &S))) return rc;
+    GC_REQUIRE(S.S > 0, GC_E_INVAL, "the mask samples nothing");
+    S.loss_p = h->loss;
     const int T = h->n_iter;
     const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
     const size_t nbuf = (size_t)S.E * S.Nc * S.Ny * S.Nz;
@@ -1324,7 +1356,6 @@ int gc_sense_recon(const gc_sense_problem* pr, const gc_adam_hyper* h, float* ou
     GC_TRY_HIP(sc.alloc_n(&hist, (size_t)T));
     GC_TRY_HIP(sc.alloc_n(&stop, 2));
     GC_TRY_HIP(fill_i32(stop, 2, 0, s));
-    S.loss_p = h->loss;
     SenseOpt O{};
     O.optimizer = h->optimizer;
     O.lr = (float)h->lr;
@@ -1342,8 +1373,8 @@ int gc_sense_recon(const gc_sense_problem* pr, const gc_adam_hyper* h, float* ou
     const double tol = h->tol > 0 ? h->tol : -INFINITY;
     double b1 = 1.0, b2 = 1.0;
     int hstop[2] = {0, 0};
-    LaunchTimer tm[kSenseStages] = {{"sense_rows_fwd", s}, {"sense_cols", s},
-                                     {"sense_rows_adj", s}, {"sense_update", s}};
+    LaunchTimer tm[kSenseStages] = {{"sense_ycols", s}, {"sense_zrows", s}};
+    GC_TRY_HIP(sense_forward_rows(S, img0, buf, s));
     for (int t = 1; t <= T; ++t) {
         b1 *= h->beta1;
         b2 *= h->beta2;
@@ -1355,7 +1386,7 @@ int gc_sense_recon(const gc_sense_problem* pr, const gc_adam_hyper* h, float* ou
         for (int k = 0; k < kSenseStages; ++k) {
             tm[k].begin();
             GC_TRY_HIP(sense_stage(k, S, O, in, out, m, v, buf, rec ? partial : nullptr,
-                                   stopping ? stop : nullptr, s));
+                                   stopping ? stop : nullptr, t < T ? 1 : 0, s));
             tm[k].end();
         }
         if (rec)
@@ -1401,15 +1432,16 @@ int gc_sense_forward(const gc_sense_problem* pr, const float* image, float* out,
     if ((rc = ds.open(exec))) return rc;
     Scratch sc(ds.stream);
     SenseDev S;
-    int64_t nsamp = 0;
-    if ((rc = sense_setup(sc, pr, ds.mem_kind, false, &S, &nsamp))) return rc;
+    if ((rc = sense_setup(sc, pr, ds.mem_kind, false, &S))) return rc;
     const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
     const size_t nbuf = (size_t)S.E * S.Nc * S.Ny * S.Nz;
     const void* di;
     if ((rc = stage_in(sc, image, (size_t)npix * 8, ds.mem_kind, &di))) return rc;
+    float2* buf = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&buf, nbuf));
     float2* dout = (float2*)out;
     if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dout, nbuf));
-    GC_TRY_HIP(sense_forward_op(S, (const float2*)di, dout, ds.stream));
+    GC_TRY_HIP(sense_forward_op(S, (const float2*)di, buf, dout, ds.stream));
     if (ds.mem_kind == GC_MEM_HOST)
         GC_TRY_HIP(hipMemcpyAsync(out, dout, nbuf * 8, hipMemcpyDeviceToHost, ds.stream));
     GC_TRY_HIP(hipStreamSynchronize(ds.stream));
@@ -1427,19 +1459,16 @@ int gc_sense_adjoint(const gc_sense_problem* pr, const float* kspace, float* out
     if ((rc = ds.open(exec))) return rc;
     Scratch sc(ds.stream);
     SenseDev S;
-    int64_t nsamp = 0;
-    if ((rc = sense_setup(sc, pr, ds.mem_kind, false, &S, &nsamp))) return rc;
+    if ((rc = sense_setup(sc, pr, ds.mem_kind, false, &S))) return rc;
     const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
     const size_t nbuf = (size_t)S.E * S.Nc * S.Ny * S.Nz;
-    // the adjoint works in place on a copy of the input
+    const void* dk;
+    if ((rc = stage_in(sc, kspace, nbuf * 8, ds.mem_kind, &dk))) return rc;
     float2* buf = nullptr;
     GC_TRY_HIP(sc.alloc_n(&buf, nbuf));
-    GC_TRY_HIP(hipMemcpyAsync(buf, kspace, nbuf * 8,
-                              ds.mem_kind == GC_MEM_HOST ? hipMemcpyHostToDevice
-                                                         : hipMemcpyDeviceToDevice, ds.stream));
     float2* dout = (float2*)out;
     if (ds.mem_kind == GC_MEM_HOST) GC_TRY_HIP(sc.alloc_n(&dout, (size_t)npix));
-    GC_TRY_HIP(sense_adjoint_op(S, buf, dout, ds.stream));
+    GC_TRY_HIP(sense_adjoint_op(S, (const float2*)dk, buf, dout, ds.stream));
     if (ds.mem_kind == GC_MEM_HOST)
         GC_TRY_HIP(hipMemcpyAsync(out, dout, (size_t)npix * 8, hipMemcpyDeviceToHost, ds.stream));
     GC_TRY_HIP(hipStreamSynchronize(ds.stream));

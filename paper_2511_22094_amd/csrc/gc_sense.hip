@@ -5,362 +5,427 @@
 // sampling mask of echo e, l = |Re r|^2 + |Im r|^2 (L2) or |Re r| + |Im r| (L1)
 // and TV2 the anisotropic 2D total variation of the real and imaginary parts.
 //
-// One iteration is four kernels over the E x Nc coil images:
-//   rows_fwd   x = C_c I_e, DFT along z (LDS, radix 2)            -> buf
-//   cols       DFT along y, residual against the measured samples,
-//              loss partials, dl/dX, inverse DFT along y (in LDS) -> buf
-//   rows_adj   inverse DFT along z, times conj(C_c)                -> buf
-//   update     sum over coils + TV subgradient, optimiser step on Re and Im
-// Sizes along y and z are powers of two up to kSenseMaxN (z at least
-// kSenseCols); the y pass works on tiles of Ny x G columns, G = min(16, 4096/Ny).
+// The E x Nc coil images live in one buffer `buf` [E][Nc][Ny][Nz] that holds,
+// between the two launches of an iteration, the coil images transformed
+// along z only.  One iteration:
+//   ycols  (block per (e, c, G columns)): DFT along y, residual against the
+//          measured samples, loss partial, dl/dX, inverse DFT along y;
+//   zrows  (block per (e, y) row, all coils): inverse DFT along z, times
+//          conj(C_c), sum over coils = gradient; TV subgradient; optimiser
+//          step; then x = C_c I_new and its DFT along z for the next
+//          iteration.
+// Each pass reads and writes `buf` once: four passes of 8 E Nc Ny Nz bytes
+// per iteration.  Transforms are four-step team FFTs (gc_fft.hpp) with one
+// LDS transpose each.  Sizes along y and z are powers of two up to
+// kSenseMaxN, z at least kSenseMinNz.
+#include "gc_fft.hpp"
 #include "gc_sense.hpp"
 
 namespace gc {
 
 namespace {
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
-    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-// complex sample loaded through the global address space as one 8-byte load
 typedef float v2f __attribute__((ext_vector_type(2)));
+// complex sample loaded through the global address space as one 8-byte load
 __device__ __forceinline__ float2 ld2(const float2* p, int64_t i) {
     const v2f t = gload((const v2f*)p)[i];
     return make_float2(t.x, t.y);
 }
-__device__ __forceinline__ unsigned bitrev(unsigned i, int logn) {
-    return __brev(i) >> (32 - logn);
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float sgnf(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
+
+// Blocks are dealt round-robin over the 8 XCDs; XCD x takes a contiguous
+// range of logical blocks so that neighbouring tiles share its L2.
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+    const int q = nblk / 8, r = nblk % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
 }
 
-// In-place radix-2 decimation-in-time transform of `cnt` interleaved
-// sequences held in LDS, element j of sequence s at x[j * cnt + s], the input
-// already in bit-reversed order.  tw[k] = exp(-2 pi i k / N); inverse uses
-// the conjugate twiddles.  All threads of the block take part.
-template <bool INV>
-__device__ __forceinline__ void fft_lds(float2* x, int N, int logn, int cnt,
-                                        const float2* __restrict__ tw) {
-    for (int s = 1; s <= logn; ++s) {
-        const int half = 1 << (s - 1);
-        const int stride = N >> s;   // twiddle index step
-        __syncthreads();
-        for (int i = threadIdx.x; i < (N >> 1) * cnt; i += blockDim.x) {
-            const int seq = i % cnt, bf = i / cnt;
-            const int k = bf & (half - 1);
-            const int a = ((bf >> (s - 1)) << s) + k;
-            const int b = a + half;
-            float2 w = ld2(tw, k * stride);
-            if (INV) w.y = -w.y;
-            const float2 xb = x[b * cnt + seq], xa = x[a * cnt + seq];
-            const float2 t = cmul(w, xb);
-            x[a * cnt + seq] = make_float2(xa.x + t.x, xa.y + t.y);
-            x[b * cnt + seq] = make_float2(xa.x - t.x, xa.y - t.y);
-        }
-    }
+// Fixed-order block sum (result in thread 0) for a power-of-two block size.
+__device__ __forceinline__ float block_sum_pow2(float v, float* red /*[4]*/) {
+    const int W = blockDim.x < 64 ? (int)blockDim.x : 64;
+    for (int o = W >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
     __syncthreads();
+    float r = 0.f;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < ((int)blockDim.x + 63) / 64; ++i) r += red[i];
+    return r;
 }
+
+// y pass geometry: G columns per block, a team of N2 threads per column.
+template <int LOG> struct YGeo {
+    using Sh = FftShape<LOG>;
+    static constexpr int G = sense_tile_cols(LOG);
+    static constexpr int THREADS = G * Sh::N2;
+    static constexpr int RS = Sh::N2 * G + G;   // float2 per k1 row of the transpose (padded)
+    static constexpr int LDS = Sh::N + Sh::N1 * RS;
+};
+// z pass geometry: TEAMS coil rows at a time, a team of N2 threads per row.
+template <int LOG> struct ZGeo {
+    using Sh = FftShape<LOG>;
+    static constexpr int T1 = 256 / Sh::N2, T2 = 4096 >> LOG;
+    static constexpr int TEAMS = T1 < T2 ? T1 : T2;
+    static constexpr int THREADS = TEAMS * Sh::N2;
+    static constexpr int RS = Sh::N2 + 1;        // float2 per k1 row of a team's transpose
+    static constexpr int AREA = Sh::N1 * RS;     // >= N: reused for the coil sum
+    static constexpr int LDS = 2 * Sh::N + TEAMS * AREA;
+};
 
 }  // namespace
 
-// ---------------------------------------------------------------- rows
-// One block per (e, c, y) row.  MODE 0: forward pass, input C_c I_e; MODE 1:
-// adjoint pass, input buf, output conj(C_c) IDFT_z(buf).
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void sense_rows_kernel(SenseDev S, const float2* __restrict__ img,
-                                                           float2* __restrict__ buf,
-                                                           const int* __restrict__ stop) {
+// ------------------------------------------------------------------ y pass
+// MODE 0: iteration (forward DFT_y, residual, dl/dX, inverse DFT_y; buf in place)
+// MODE 1: operator tail (forward DFT_y of buf, zero outside the mask, to out)
+// MODE 2: adjoint head (input r zeroed outside the mask, inverse DFT_y, to buf)
+template <int LOGY, int MODE>
+__global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const float2* __restrict__ in,
+                                                         float2* __restrict__ buf,
+                                                         float2* __restrict__ out,
+                                                         float* __restrict__ partial,
+                                                         const int* __restrict__ stop) {
+    using Sh = FftShape<LOGY>;
+    using Geo = YGeo<LOGY>;
+    constexpr int N = Sh::N, N1 = Sh::N1, N2 = Sh::N2, G = Geo::G;
     extern __shared__ float2 lds[];
-    if (stop && stop[0] != 0) return;
-    const int Ny = S.Ny, Nz = S.Nz;
-    const int row = blockIdx.x;                  // ((e Nc + c) Ny + y)
-    const int y = row % Ny, ec = row / Ny;
-    const int c = ec % S.Nc, e = ec / S.Nc;
-    const float2* C = S.coils + ((int64_t)c * Ny + y) * Nz;
-    float2* out = buf + (int64_t)row * Nz;
-    for (int z = threadIdx.x; z < Nz; z += blockDim.x) {
-        float2 v;
-        if (MODE == 0) v = cmul(ld2(C, z), ld2(img, ((int64_t)e * Ny + y) * Nz + z));
-        else v = out[z];
-        lds[bitrev(z, S.logNz)] = v;
-    }
-    fft_lds<MODE == 1>(lds, Nz, S.logNz, 1, S.twz);
-    const float sc = S.rsqrtNz;
-    for (int z = threadIdx.x; z < Nz; z += blockDim.x) {
-        float2 v = lds[z];
-        v.x *= sc;
-        v.y *= sc;
-        if (MODE == 1) v = cmulc(v, ld2(C, z));
-        out[z] = v;
-    }
-}
-
-// ---------------------------------------------------------------- columns
-// One block per (e, c, group of G columns).  Forward DFT along y;
-// r = X - k on sampled entries; loss partial; dl/dX scaled by 1/Nk; inverse
-// DFT along y; back to buf.
-__global__ __launch_bounds__(kBlock) void sense_cols_kernel(SenseDev S, float2* __restrict__ buf,
-                                                           float* __restrict__ partial,
-                                                           const int* __restrict__ stop) {
-    extern __shared__ float2 lds[];
-    __shared__ float red[kBlock / 64];
-    if (stop && stop[0] != 0) return;
-    const int Ny = S.Ny, Nz = S.Nz, G = S.G;
-    const int ngrp = Nz / G;
-    const int ec = blockIdx.x / ngrp, z0 = (blockIdx.x % ngrp) * G;
-    const int e = ec / S.Nc;
-    float2* base = buf + (int64_t)ec * Ny * Nz;
-    float2* A = lds;             // [Ny][G]
-    for (int i = threadIdx.x; i < Ny * G; i += blockDim.x) {
-        const int y = i / G, j = i % G;
-        A[bitrev(y, S.logNy) * G + j] = base[(int64_t)y * Nz + z0 + j];
-    }
-    fft_lds<false>(A, Ny, S.logNy, G, S.twy);
-    const float sc = S.rsqrtNy;
-    const float2* K = S.ksp + (int64_t)ec * Ny * Nz;
-    const uint8_t* Mk = S.mask + (int64_t)e * Ny * Nz;
-    float lsum = 0.f;
-    // residual and dl/dX in place (natural order) ...
-    for (int i = threadIdx.x; i < Ny * G; i += blockDim.x) {
-        const int y = i / G, j = i % G;
-        const int64_t a = (int64_t)y * Nz + z0 + j;
-        float2 d = make_float2(0.f, 0.f);
-        if (gload(Mk)[a]) {
-            const float2 X = A[i];
-            const float2 k = ld2(K, a);
-            const float rx = X.x * sc - k.x, ry = X.y * sc - k.y;
-            if (S.loss_p == 2) {
-                lsum += rx * rx + ry * ry;
-                d = make_float2(2.f * rx * S.scale_data, 2.f * ry * S.scale_data);
-            } else {
-                lsum += fabsf(rx) + fabsf(ry);
-                d = make_float2((rx > 0.f ? 1.f : (rx < 0.f ? -1.f : 0.f)) * S.scale_data,
-                                (ry > 0.f ? 1.f : (ry < 0.f ? -1.f : 0.f)) * S.scale_data);
-            }
-        }
-        A[i] = d;
-    }
-    // ... then into bit-reversed order by pairwise swaps, for the inverse DFT
+    __shared__ float red[4];
+    if (stop && stop[0] != 0) return;   // uniform
+    const int nzg = S.Nz / G;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int ec = blk / nzg, z0 = (blk % nzg) * G;
+    const int e = ec / S.Nc, c = ec % S.Nc;
+    const int t = threadIdx.x, j = t % G, p = t / G;
+    float2* tw = lds;
+    float2* T = lds + N + j;
+    for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twy, i);
     __syncthreads();
-    for (int i = threadIdx.x; i < Ny * G; i += blockDim.x) {
-        const int y = i / G, j = i % G;
-        const int r = (int)bitrev(y, S.logNy);
-        if (y < r) {
-            const float2 t = A[y * G + j];
-            A[y * G + j] = A[r * G + j];
-            A[r * G + j] = t;
+    const int64_t Nz = S.Nz;
+    const int z = z0 + j;
+    const int64_t col = (int64_t)ec * S.Ny * Nz + z;        // element y at col + y Nz
+    const uint32_t bit = 1u << j;
+    const int64_t tile = (int64_t)e * nzg + z0 / G;
+    const uint32_t* ti = S.tinfo + tile * S.Ny;              // row y of this tile at ti[y]
+    float2 a[N1];
+    if (MODE == 2) {
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int y = p + N2 * n1;
+            a[n1] = (gload(ti)[y] & bit) ? ld2(in, col + y * Nz) : make_float2(0.f, 0.f);
+        }
+    } else {
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) a[n1] = ld2(buf, col + (int64_t)(p + N2 * n1) * Nz);
+        fft_team<LOGY, false>(a, p, T, Geo::RS, G, tw);
+    }
+    const float sc = S.rsqrtNy;
+    if (MODE == 1) {
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int y = p + N2 * n1;
+            const bool smp = (gload(ti)[y] & bit) != 0;
+            out[col + y * Nz] = smp ? make_float2(a[n1].x * sc, a[n1].y * sc) : make_float2(0.f, 0.f);
+        }
+        return;
+    }
+    float lsum = 0.f;
+    if (MODE == 0) {
+        const float2* kc = S.kc + (int64_t)c * S.S + gload(S.tbase)[tile];
+        const float sd = S.scale_data;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int y = p + N2 * n1;
+            const uint32_t word = gload(ti)[y];
+            float2 d = make_float2(0.f, 0.f);
+            if (word & bit) {
+                const int s = (int)(word >> 16) + __popc(word & (bit - 1u));
+                const float2 k = ld2(kc, s);
+                const float rx = a[n1].x * sc - k.x, ry = a[n1].y * sc - k.y;
+                if (S.loss_p == 2) {
+                    lsum += rx * rx + ry * ry;
+                    d = make_float2(2.f * rx * sd, 2.f * ry * sd);
+                } else {
+                    lsum += fabsf(rx) + fabsf(ry);
+                    d = make_float2(sgnf(rx) * sd, sgnf(ry) * sd);
+                }
+            }
+            a[n1] = d;
         }
     }
-    fft_lds<true>(A, Ny, S.logNy, G, S.twy);
-    for (int i = threadIdx.x; i < Ny * G; i += blockDim.x) {
-        const int y = i / G, j = i % G;
-        float2 v = A[i];
-        v.x *= sc;
-        v.y *= sc;
-        base[(int64_t)y * Nz + z0 + j] = v;
+    fft_team<LOGY, true>(a, p, T, Geo::RS, G, tw);
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1)
+        buf[col + (int64_t)(p + N2 * n1) * Nz] = make_float2(a[n1].x * sc, a[n1].y * sc);
+    if (MODE == 0 && partial) {
+        const float s = block_sum_pow2(lsum * S.scale_data, red);
+        if (t == 0) partial[blockIdx.x] = s;
     }
-    const float s = block_sum(lsum * S.scale_data, red);
-    if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
 }
 
-// ---------------------------------------------------------------- update
-// One thread per image pixel (e, y, z): gradient = sum over coils of buf +
-// TV subgradient of Re and Im (forward differences along y and z within the
-// echo image, lambda / Npix); optimiser step; TV loss partial.
-__global__ __launch_bounds__(kBlock) void sense_update_kernel(SenseDev S, SenseOpt O,
-                                                             const float2* __restrict__ img_in,
-                                                             float2* __restrict__ img_out,
-                                                             float2* __restrict__ m,
-                                                             float2* __restrict__ v,
-                                                             const float2* __restrict__ buf,
-                                                             float* __restrict__ partial,
-                                                             const int* __restrict__ stop) {
-    __shared__ float red[kBlock / 64];
-    if (stop && stop[0] != 0) return;
-    const int Ny = S.Ny, Nz = S.Nz;
-    const int64_t npix = (int64_t)S.E * Ny * Nz;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+// ------------------------------------------------------------------ z pass
+// MODE 0: iteration (gradient from buf, TV, optimiser step img_in -> img_out;
+//         with fwd, the next iteration's forward rows into buf)
+// MODE 1: operator head (forward rows of img_in into buf)
+// MODE 2: adjoint tail (sum over coils of conj(C_c) F_z^H(buf), to out)
+template <int LOGZ, int MODE>
+__global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O,
+                                                         const float2* __restrict__ img_in,
+                                                         float2* __restrict__ img_out,
+                                                         float2* __restrict__ m,
+                                                         float2* __restrict__ v,
+                                                         float2* __restrict__ buf,
+                                                         float2* __restrict__ out,
+                                                         float* __restrict__ partial,
+                                                         const int* __restrict__ stop, int fwd) {
+    using Sh = FftShape<LOGZ>;
+    using Geo = ZGeo<LOGZ>;
+    constexpr int N = Sh::N, N1 = Sh::N1, N2 = Sh::N2, TEAMS = Geo::TEAMS;
+    extern __shared__ float2 lds[];
+    __shared__ float red[4];
+    if (stop && stop[0] != 0) return;   // uniform
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int y = blk / S.E, e = blk % S.E;   // the echoes of one row are neighbours
+    const int t = threadIdx.x, tau = t / N2, p = t % N2;
+    const int Ny = S.Ny, Nc = S.Nc;
+    float2* tw = lds;
+    float2* U = lds + N;
+    float2* T = lds + 2 * N;
+    float2* Tt = T + tau * Geo::AREA;
+    for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twz, i);
+    const int64_t row = ((int64_t)e * Ny + y) * N;   // image row (e, y)
+    if (MODE == 1)
+        for (int z = t; z < N; z += Geo::THREADS) U[z] = ld2(img_in, row + z);
+    __syncthreads();
+    const float sc = S.rsqrtNz;
     float tvl = 0.f;
-    if (p < npix) {
-        const int z = (int)(p % Nz), y = (int)((p / Nz) % Ny), e = (int)(p / ((int64_t)Ny * Nz));
-        float2 g = make_float2(0.f, 0.f);
-        for (int c = 0; c < S.Nc; ++c) {
-            const float2 t = ld2(buf, (((int64_t)e * S.Nc + c) * Ny + y) * Nz + z);
-            g.x += t.x;
-            g.y += t.y;
+    if (MODE != 1) {
+        float2 acc[N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) acc[n1] = make_float2(0.f, 0.f);
+        for (int cb = 0; cb < Nc; cb += TEAMS) {   // uniform trip count (barriers inside)
+            const int c = cb + tau;
+            const bool live = c < Nc;
+            const int64_t crow = (((int64_t)e * Nc + c) * Ny + y) * N;
+            float2 a[N1];
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1)
+                a[n1] = live ? ld2(buf, crow + p + N2 * n1) : make_float2(0.f, 0.f);
+            fft_team<LOGZ, true>(a, p, Tt, Geo::RS, 1, tw);
+            if (live) {
+                const int64_t srow = ((int64_t)c * Ny + y) * N;
+#pragma unroll
+                for (int n1 = 0; n1 < N1; ++n1) {
+                    const float2 q = cmulc(a[n1], ld2(S.coils, srow + p + N2 * n1));
+                    acc[n1].x += q.x;
+                    acc[n1].y += q.y;
+                }
+            }
         }
-        const float2 u = ld2(img_in, p);
-        if (O.scale_tv != 0.f) {
-            float gx = 0.f, gy = 0.f, R = 0.f;
-            auto sg = [](float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); };
-            // forward neighbours: pairs (p, q)
-            if (z + 1 < Nz) {
-                const float2 q = ld2(img_in, p + 1);
-                R += fabsf(q.x - u.x) + fabsf(q.y - u.y);
-                gx -= sg(q.x - u.x);
-                gy -= sg(q.y - u.y);
+        __syncthreads();   // every team is done with its transpose area
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) Tt[p + N2 * n1] = acc[n1];
+        __syncthreads();
+        for (int z = t; z < N; z += Geo::THREADS) {
+            float2 g = make_float2(0.f, 0.f);
+            for (int k = 0; k < TEAMS; ++k) {   // fixed order
+                const float2 q = T[k * Geo::AREA + z];
+                g.x += q.x;
+                g.y += q.y;
             }
-            if (y + 1 < Ny) {
-                const float2 q = ld2(img_in, p + Nz);
-                R += fabsf(q.x - u.x) + fabsf(q.y - u.y);
-                gx -= sg(q.x - u.x);
-                gy -= sg(q.y - u.y);
+            g.x *= sc;
+            g.y *= sc;
+            if (MODE == 2) {
+                out[row + z] = g;
+                continue;
             }
-            // backward neighbours: pairs (q, p)
-            if (z > 0) {
-                const float2 q = ld2(img_in, p - 1);
-                gx += sg(u.x - q.x);
-                gy += sg(u.y - q.y);
+            const float2 u = ld2(img_in, row + z);
+            if (O.scale_tv != 0.f) {
+                float gx = 0.f, gy = 0.f, R = 0.f;
+                if (z + 1 < N) {   // forward neighbours: pairs (u, q)
+                    const float2 q = ld2(img_in, row + z + 1);
+                    R += fabsf(q.x - u.x) + fabsf(q.y - u.y);
+                    gx -= sgnf(q.x - u.x);
+                    gy -= sgnf(q.y - u.y);
+                }
+                if (y + 1 < Ny) {
+                    const float2 q = ld2(img_in, row + N + z);
+                    R += fabsf(q.x - u.x) + fabsf(q.y - u.y);
+                    gx -= sgnf(q.x - u.x);
+                    gy -= sgnf(q.y - u.y);
+                }
+                if (z > 0) {       // backward neighbours: pairs (q, u)
+                    const float2 q = ld2(img_in, row + z - 1);
+                    gx += sgnf(u.x - q.x);
+                    gy += sgnf(u.y - q.y);
+                }
+                if (y > 0) {
+                    const float2 q = ld2(img_in, row - N + z);
+                    gx += sgnf(u.x - q.x);
+                    gy += sgnf(u.y - q.y);
+                }
+                g.x += O.scale_tv * gx;
+                g.y += O.scale_tv * gy;
+                tvl += O.scale_tv * R;
             }
-            if (y > 0) {
-                const float2 q = ld2(img_in, p - Nz);
-                gx += sg(u.x - q.x);
-                gy += sg(u.y - q.y);
-            }
-            g.x += O.scale_tv * gx;
-            g.y += O.scale_tv * gy;
-            tvl = O.scale_tv * R;
+            float2 mm = m[row + z], vv = v[row + z], un;
+            auto step = [&](float uu, float gg, float& mk, float& vk) -> float {
+                if (O.optimizer == 0) {
+                    mk = O.beta1 * mk + O.omb1 * gg;
+                    vk = O.beta2 * vk + O.omb2 * gg * gg;
+                    return uu - O.lr * (mk * O.c1) / (sqrtf(vk * O.c2) + O.eps);
+                } else if (O.optimizer == 1) {
+                    mk = O.momentum * mk - O.lr * gg;
+                    return uu + mk;
+                }
+                vk = O.rho * vk + O.omrho * gg * gg;
+                return uu - O.lr * gg / (sqrtf(vk) + O.eps);
+            };
+            un.x = step(u.x, g.x, mm.x, vv.x);
+            un.y = step(u.y, g.y, mm.y, vv.y);
+            img_out[row + z] = un;
+            m[row + z] = mm;
+            v[row + z] = vv;
+            U[z] = un;
         }
-        float2 mm = m[p], vv = v[p], un;
-        auto step = [&](float uu, float gg, float& mk, float& vk) -> float {
-            if (O.optimizer == 0) {
-                mk = O.beta1 * mk + O.omb1 * gg;
-                vk = O.beta2 * vk + O.omb2 * gg * gg;
-                return uu - O.lr * (mk * O.c1) / (sqrtf(vk * O.c2) + O.eps);
-            } else if (O.optimizer == 1) {
-                mk = O.momentum * mk - O.lr * gg;
-                return uu + mk;
-            }
-            vk = O.rho * vk + O.omrho * gg * gg;
-            return uu - O.lr * gg / (sqrtf(vk) + O.eps);
-        };
-        un.x = step(u.x, g.x, mm.x, vv.x);
-        un.y = step(u.y, g.y, mm.y, vv.y);
-        img_out[p] = un;
-        m[p] = mm;
-        v[p] = vv;
     }
-    if (partial) {
-        const float s = block_sum(tvl, red);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (MODE == 2) return;
+    if (MODE == 0 && partial) {
+        const float s = block_sum_pow2(tvl, red);
+        if (t == 0) partial[blockIdx.x] = s;
+    }
+    if (MODE == 1 || fwd) {
+        __syncthreads();   // U complete
+        for (int cb = 0; cb < Nc; cb += TEAMS) {
+            const int c = cb + tau;
+            const bool live = c < Nc;
+            const int64_t srow = ((int64_t)c * Ny + y) * N;
+            float2 a[N1];
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) {
+                const int z = p + N2 * n1;
+                a[n1] = live ? fft_cmul(ld2(S.coils, srow + z), U[z]) : make_float2(0.f, 0.f);
+            }
+            fft_team<LOGZ, false>(a, p, Tt, Geo::RS, 1, tw);
+            if (live) {
+                const int64_t crow = (((int64_t)e * Nc + c) * Ny + y) * N;
+#pragma unroll
+                for (int n1 = 0; n1 < N1; ++n1)
+                    buf[crow + p + N2 * n1] = make_float2(a[n1].x * sc, a[n1].y * sc);
+            }
+        }
     }
 }
 
-// Pure operators (autograd building blocks): forward A(I) and adjoint A^H(r).
-__global__ __launch_bounds__(kBlock) void sense_mask_kernel(SenseDev S, float2* __restrict__ buf) {
-    const int64_t n = (int64_t)S.E * S.Nc * S.Ny * S.Nz;
+// -------------------------------------------------------- k-space packing
+__global__ __launch_bounds__(kBlock) void sense_pack_kernel(SenseDev S, const float2* __restrict__ dense,
+                                                           float2* __restrict__ kc) {
+    const int64_t NN = (int64_t)S.Ny * S.Nz;
+    const int64_t n = (int64_t)S.E * S.Nc * NN;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const int64_t pix = i % ((int64_t)S.Ny * S.Nz);
-    const int e = (int)(i / ((int64_t)S.Nc * S.Ny * S.Nz));
-    if (!gload(S.mask)[(int64_t)e * S.Ny * S.Nz + pix]) buf[i] = make_float2(0.f, 0.f);
+    const int z = (int)(i % S.Nz);
+    const int y = (int)((i / S.Nz) % S.Ny);
+    const int64_t ec = i / NN;
+    const int c = (int)(ec % S.Nc), e = (int)(ec / S.Nc);
+    const int64_t tile = (int64_t)e * (S.Nz / S.G) + z / S.G;
+    const uint32_t word = gload(S.tinfo)[tile * S.Ny + y], bit = 1u << (z % S.G);
+    if (!(word & bit)) return;
+    const int64_t s = (int64_t)gload(S.tbase)[tile] + (word >> 16) + __popc(word & (bit - 1u));
+    kc[(int64_t)c * S.S + s] = ld2(dense, i);
 }
 
-template <bool INV>
-__global__ __launch_bounds__(kBlock) void sense_cols_plain_kernel(SenseDev S, float2* __restrict__ buf) {
-    extern __shared__ float2 lds[];
-    const int Ny = S.Ny, Nz = S.Nz, G = S.G;
-    const int ngrp = Nz / G;
-    const int ec = blockIdx.x / ngrp, z0 = (blockIdx.x % ngrp) * G;
-    float2* base = buf + (int64_t)ec * Ny * Nz;
-    for (int i = threadIdx.x; i < Ny * G; i += blockDim.x) {
-        const int y = i / G, j = i % G;
-        lds[bitrev(y, S.logNy) * G + j] = base[(int64_t)y * Nz + z0 + j];
-    }
-    fft_lds<INV>(lds, Ny, S.logNy, G, S.twy);
-    for (int i = threadIdx.x; i < Ny * G; i += blockDim.x) {
-        const int y = i / G, j = i % G;
-        float2 v = lds[i];
-        v.x *= S.rsqrtNy;
-        v.y *= S.rsqrtNy;
-        base[(int64_t)y * Nz + z0 + j] = v;
+// ------------------------------------------------------------------ launchers
+namespace {
+
+template <int LOGY, int MODE>
+hipError_t launch_y(const SenseDev& S, const float2* in, float2* buf, float2* out, float* partial,
+                    const int* stop, hipStream_t s) {
+    using Geo = YGeo<LOGY>;
+    const int nblk = S.E * S.Nc * (S.Nz / Geo::G);
+    hipLaunchKernelGGL((sense_ycols_kernel<LOGY, MODE>), dim3(nblk), dim3(Geo::THREADS),
+                       Geo::LDS * sizeof(float2), s, S, in, buf, out, partial, stop);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t dispatch_y(const SenseDev& S, const float2* in, float2* buf, float2* out, float* partial,
+                      const int* stop, hipStream_t s) {
+    switch (S.logNy) {
+#define GC_Y(L) \
+    case L: return launch_y<L, MODE>(S, in, buf, out, partial, stop, s);
+        GC_Y(1) GC_Y(2) GC_Y(3) GC_Y(4) GC_Y(5) GC_Y(6) GC_Y(7) GC_Y(8) GC_Y(9) GC_Y(10)
+#undef GC_Y
+    default: return hipErrorInvalidValue;
     }
 }
 
-// adjoint combine: out[e] = sum_c buf[e][c]
-__global__ __launch_bounds__(kBlock) void sense_coil_sum_kernel(SenseDev S, const float2* __restrict__ buf,
-                                                               float2* __restrict__ out) {
-    const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= npix) return;
-    const int64_t pix = p % ((int64_t)S.Ny * S.Nz);
-    const int e = (int)(p / ((int64_t)S.Ny * S.Nz));
-    float2 g = make_float2(0.f, 0.f);
-    for (int c = 0; c < S.Nc; ++c) {
-        const float2 t = ld2(buf, ((int64_t)e * S.Nc + c) * S.Ny * S.Nz + pix);
-        g.x += t.x;
-        g.y += t.y;
-    }
-    out[p] = g;
+template <int LOGZ, int MODE>
+hipError_t launch_z(const SenseDev& S, const SenseOpt& O, const float2* img_in, float2* img_out,
+                    float2* m, float2* v, float2* buf, float2* out, float* partial,
+                    const int* stop, int fwd, hipStream_t s) {
+    using Geo = ZGeo<LOGZ>;
+    const int nblk = S.E * S.Ny;
+    hipLaunchKernelGGL((sense_zrows_kernel<LOGZ, MODE>), dim3(nblk), dim3(Geo::THREADS),
+                       Geo::LDS * sizeof(float2), s, S, O, img_in, img_out, m, v, buf, out,
+                       partial, stop, fwd);
+    return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- launchers
-static size_t rows_lds(const SenseDev& S) { return (size_t)S.Nz * sizeof(float2); }
-static size_t cols_lds(const SenseDev& S, int bufs) {
-    return (size_t)bufs * S.Ny * S.G * sizeof(float2);
+template <int MODE>
+hipError_t dispatch_z(const SenseDev& S, const SenseOpt& O, const float2* img_in,
+                      float2* img_out, float2* m, float2* v, float2* buf, float2* out,
+                      float* partial, const int* stop, int fwd, hipStream_t s) {
+    switch (S.logNz) {
+#define GC_Z(L) \
+    case L: return launch_z<L, MODE>(S, O, img_in, img_out, m, v, buf, out, partial, stop, fwd, s);
+        GC_Z(4) GC_Z(5) GC_Z(6) GC_Z(7) GC_Z(8) GC_Z(9) GC_Z(10)
+#undef GC_Z
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int ycols_blocks(const SenseDev& S) { return S.E * S.Nc * (S.Nz / sense_tile_cols(S.logNy)); }
+
+}  // namespace
+
+hipError_t sense_pack_kspace(const SenseDev& S, const float2* dense, float2* kc, hipStream_t s) {
+    const int64_t n = (int64_t)S.E * S.Nc * S.Ny * S.Nz;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(sense_pack_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, S, dense, kc);
+    return hipGetLastError();
+}
+
+hipError_t sense_forward_rows(const SenseDev& S, const float2* img, float2* buf, hipStream_t s) {
+    return dispatch_z<1>(S, SenseOpt{}, img, nullptr, nullptr, nullptr, buf, nullptr, nullptr,
+                         nullptr, 1, s);
 }
 
 hipError_t sense_stage(int stage, const SenseDev& S, const SenseOpt& O, const float2* img_in,
                        float2* img_out, float2* m, float2* v, float2* buf, float* partial,
-                       const int* stop, hipStream_t s) {
-    const int nrow = S.E * S.Nc * S.Ny;
-    const int ncol = S.E * S.Nc * (S.Nz / S.G);
-    const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
-    const int nupd = (int)((npix + kBlock - 1) / kBlock);
-    switch (stage) {
-    case 0:
-        hipLaunchKernelGGL(sense_rows_kernel<0>, dim3(nrow), dim3(kBlock), rows_lds(S), s, S,
-                           img_in, buf, stop);
-        break;
-    case 1:
-        hipLaunchKernelGGL(sense_cols_kernel, dim3(ncol), dim3(kBlock), cols_lds(S, 1), s, S, buf,
-                           partial, stop);
-        break;
-    case 2:
-        hipLaunchKernelGGL(sense_rows_kernel<1>, dim3(nrow), dim3(kBlock), rows_lds(S), s, S,
-                           nullptr, buf, stop);
-        break;
-    default:
-        hipLaunchKernelGGL(sense_update_kernel, dim3(nupd), dim3(kBlock), 0, s, S, O, img_in,
-                           img_out, m, v, buf, partial ? partial + ncol : nullptr, stop);
-    }
-    return hipGetLastError();
+                       const int* stop, int fwd, hipStream_t s) {
+    if (stage == 0) return dispatch_y<0>(S, nullptr, buf, nullptr, partial, stop, s);
+    return dispatch_z<0>(S, O, img_in, img_out, m, v, buf, nullptr,
+                         partial ? partial + ycols_blocks(S) : nullptr, stop, fwd, s);
 }
 
-int64_t sense_partials(const SenseDev& S) {
-    const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
-    return (int64_t)S.E * S.Nc * (S.Nz / S.G) + (npix + kBlock - 1) / kBlock;
-}
+int64_t sense_partials(const SenseDev& S) { return (int64_t)ycols_blocks(S) + (int64_t)S.E * S.Ny; }
 
-hipError_t sense_forward_op(const SenseDev& S, const float2* img, float2* out, hipStream_t s) {
-    const int nrow = S.E * S.Nc * S.Ny;
-    const int ncol = S.E * S.Nc * (S.Nz / S.G);
-    const int64_t n = (int64_t)S.E * S.Nc * S.Ny * S.Nz;
-    hipLaunchKernelGGL(sense_rows_kernel<0>, dim3(nrow), dim3(kBlock), rows_lds(S), s, S, img, out,
-                       nullptr);
-    hipLaunchKernelGGL(sense_cols_plain_kernel<false>, dim3(ncol), dim3(kBlock), cols_lds(S, 1), s,
-                       S, out);
-    hipLaunchKernelGGL(sense_mask_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, S, out);
-    return hipGetLastError();
-}
-
-hipError_t sense_adjoint_op(const SenseDev& S, float2* buf /* in: r, clobbered */, float2* out,
+hipError_t sense_forward_op(const SenseDev& S, const float2* img, float2* buf, float2* out,
                             hipStream_t s) {
-    const int nrow = S.E * S.Nc * S.Ny;
-    const int ncol = S.E * S.Nc * (S.Nz / S.G);
-    const int64_t n = (int64_t)S.E * S.Nc * S.Ny * S.Nz;
-    const int64_t npix = (int64_t)S.E * S.Ny * S.Nz;
-    hipLaunchKernelGGL(sense_mask_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, S, buf);
-    hipLaunchKernelGGL(sense_cols_plain_kernel<true>, dim3(ncol), dim3(kBlock), cols_lds(S, 1), s,
-                       S, buf);
-    hipLaunchKernelGGL(sense_rows_kernel<1>, dim3(nrow), dim3(kBlock), rows_lds(S), s, S, nullptr,
-                       buf, nullptr);
-    hipLaunchKernelGGL(sense_coil_sum_kernel, dim3((unsigned)((npix + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, S, buf, out);
-    return hipGetLastError();
+    hipError_t e = sense_forward_rows(S, img, buf, s);
+    if (e != hipSuccess) return e;
+    return dispatch_y<1>(S, nullptr, buf, out, nullptr, nullptr, s);
+}
+
+hipError_t sense_adjoint_op(const SenseDev& S, const float2* r, float2* buf, float2* out,
+                            hipStream_t s) {
+    hipError_t e = dispatch_y<2>(S, r, buf, nullptr, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
+    return dispatch_z<2>(S, SenseOpt{}, nullptr, nullptr, nullptr, nullptr, buf, out, nullptr,
+                         nullptr, 0, s);
 }
 
 }  // namespace gc
