@@ -67,6 +67,14 @@ MEASURED_TRAFFIC = {
         "sha256": "1db4d4b6b8934f476cd244f9e1ba25adccfb9c44a8389ee9aaad04ca1fc362ce",
         "read_bytes": 126873332, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
+    "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
+        "sha256": "6d1e4f4e726910a13bece9e9eb3b2d820d307c346fc19cdb1d0078bf4af9525b",
+        "read_bytes": 112491638, "write_bytes": 100663501,
+        "profile": "profiles/sense_ycols_6x32_256x256.md"},
+    "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
+        "sha256": "6d1e4f4e726910a13bece9e9eb3b2d820d307c346fc19cdb1d0078bf4af9525b",
+        "read_bytes": 142073075, "write_bytes": 109899252,
+        "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
 
