@@ -31,6 +31,12 @@ __device__ __forceinline__ float2 ld2(const float2* p, int64_t i) {
     const v2f t = gload((const v2f*)p)[i];
     return make_float2(t.x, t.y);
 }
+// The same from a block-uniform base with a 32-bit offset (one address
+// register per load instead of two).
+__device__ __forceinline__ float2 ld2u(const float2* p, uint32_t i) {
+    const v2f t = gload((const v2f*)p)[i];
+    return make_float2(t.x, t.y);
+}
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
     return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
@@ -102,9 +108,10 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
     float2* T = lds + N + j;
     for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twy, i);
     __syncthreads();
-    const int64_t Nz = S.Nz;
+    const uint32_t Nz = S.Nz;
     const int z = z0 + j;
-    const int64_t col = (int64_t)ec * S.Ny * Nz + z;        // element y at col + y Nz
+    const int64_t img = (int64_t)ec * S.Ny * Nz;            // this coil image (block-uniform)
+    float2* bimg = buf + img;                               // element (y, z) at y Nz + z
     const uint32_t bit = 1u << j;
     const int64_t tile = (int64_t)e * nzg + z0 / G;
     const uint32_t* ti = S.tinfo + tile * S.Ny;              // row y of this tile at ti[y]
@@ -113,11 +120,11 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) {
             const int y = p + N2 * n1;
-            a[n1] = (gload(ti)[y] & bit) ? ld2(in, col + y * Nz) : make_float2(0.f, 0.f);
+            a[n1] = (gload(ti)[y] & bit) ? ld2u(in + img, y * Nz + z) : make_float2(0.f, 0.f);
         }
     } else {
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) a[n1] = ld2(buf, col + (int64_t)(p + N2 * n1) * Nz);
+        for (int n1 = 0; n1 < N1; ++n1) a[n1] = ld2u(bimg, (p + N2 * n1) * Nz + z);
         fft_team<LOGY, false>(a, p, T, Geo::RS, G, tw);
     }
     const float sc = S.rsqrtNy;
@@ -126,7 +133,8 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
         for (int n1 = 0; n1 < N1; ++n1) {
             const int y = p + N2 * n1;
             const bool smp = (gload(ti)[y] & bit) != 0;
-            out[col + y * Nz] = smp ? make_float2(a[n1].x * sc, a[n1].y * sc) : make_float2(0.f, 0.f);
+            out[img + y * Nz + z] =
+                smp ? make_float2(a[n1].x * sc, a[n1].y * sc) : make_float2(0.f, 0.f);
         }
         return;
     }
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
             float2 d = make_float2(0.f, 0.f);
             if (word & bit) {
                 const int s = (int)(word >> 16) + __popc(word & (bit - 1u));
-                const float2 k = ld2(kc, s);
+                const float2 k = ld2u(kc, (uint32_t)s);
                 const float rx = a[n1].x * sc - k.x, ry = a[n1].y * sc - k.y;
                 if (S.loss_p == 2) {
                     lsum += rx * rx + ry * ry;
@@ -157,7 +165,7 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
     fft_team<LOGY, true>(a, p, T, Geo::RS, G, tw);
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1)
-        buf[col + (int64_t)(p + N2 * n1) * Nz] = make_float2(a[n1].x * sc, a[n1].y * sc);
+        bimg[(p + N2 * n1) * Nz + z] = make_float2(a[n1].x * sc, a[n1].y * sc);
     if (MODE == 0 && partial) {
         const float s = block_sum_pow2(lsum * S.scale_data, red);
         if (t == 0) partial[blockIdx.x] = s;
@@ -194,9 +202,10 @@ __global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O
     float2* T = lds + 2 * N;
     float2* Tt = T + tau * Geo::AREA;
     for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twz, i);
-    const int64_t row = ((int64_t)e * Ny + y) * N;   // image row (e, y)
+    const int64_t row = ((int64_t)e * Ny + y) * N;   // image row (e, y), block-uniform
+    const uint32_t cstride = (uint32_t)Ny * N;        // coil to coil within buf and the maps
     if (MODE == 1)
-        for (int z = t; z < N; z += Geo::THREADS) U[z] = ld2(img_in, row + z);
+        for (int z = t; z < N; z += Geo::THREADS) U[z] = ld2u(img_in + row, z);
     __syncthreads();
     const float sc = S.rsqrtNz;
     float tvl = 0.f;
@@ -207,17 +216,18 @@ __global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O
         for (int cb = 0; cb < Nc; cb += TEAMS) {   // uniform trip count (barriers inside)
             const int c = cb + tau;
             const bool live = c < Nc;
-            const int64_t crow = (((int64_t)e * Nc + c) * Ny + y) * N;
+            const float2* bb = buf + (((int64_t)e * Nc + cb) * Ny + y) * N;   // block-uniform
+            const float2* cm = S.coils + ((int64_t)cb * Ny + y) * N;
+            const uint32_t o = tau * cstride + p;
             float2 a[N1];
 #pragma unroll
             for (int n1 = 0; n1 < N1; ++n1)
-                a[n1] = live ? ld2(buf, crow + p + N2 * n1) : make_float2(0.f, 0.f);
+                a[n1] = live ? ld2u(bb, o + N2 * n1) : make_float2(0.f, 0.f);
             fft_team<LOGZ, true>(a, p, Tt, Geo::RS, 1, tw);
             if (live) {
-                const int64_t srow = ((int64_t)c * Ny + y) * N;
 #pragma unroll
                 for (int n1 = 0; n1 < N1; ++n1) {
-                    const float2 q = cmulc(a[n1], ld2(S.coils, srow + p + N2 * n1));
+                    const float2 q = cmulc(a[n1], ld2u(cm, o + N2 * n1));
                     acc[n1].x += q.x;
                     acc[n1].y += q.y;
                 }
@@ -240,28 +250,29 @@ __global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O
                 out[row + z] = g;
                 continue;
             }
-            const float2 u = ld2(img_in, row + z);
+            const float2* irow = img_in + row;
+            const float2 u = ld2u(irow, z);
             if (O.scale_tv != 0.f) {
                 float gx = 0.f, gy = 0.f, R = 0.f;
                 if (z + 1 < N) {   // forward neighbours: pairs (u, q)
-                    const float2 q = ld2(img_in, row + z + 1);
+                    const float2 q = ld2u(irow, z + 1);
                     R += fabsf(q.x - u.x) + fabsf(q.y - u.y);
                     gx -= sgnf(q.x - u.x);
                     gy -= sgnf(q.y - u.y);
                 }
                 if (y + 1 < Ny) {
-                    const float2 q = ld2(img_in, row + N + z);
+                    const float2 q = ld2u(irow + N, z);
                     R += fabsf(q.x - u.x) + fabsf(q.y - u.y);
                     gx -= sgnf(q.x - u.x);
                     gy -= sgnf(q.y - u.y);
                 }
                 if (z > 0) {       // backward neighbours: pairs (q, u)
-                    const float2 q = ld2(img_in, row + z - 1);
+                    const float2 q = ld2u(irow, z - 1);
                     gx += sgnf(u.x - q.x);
                     gy += sgnf(u.y - q.y);
                 }
                 if (y > 0) {
-                    const float2 q = ld2(img_in, row - N + z);
+                    const float2 q = ld2u(irow - N, z);
                     gx += sgnf(u.x - q.x);
                     gy += sgnf(u.y - q.y);
                 }
@@ -300,19 +311,19 @@ __global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O
         for (int cb = 0; cb < Nc; cb += TEAMS) {
             const int c = cb + tau;
             const bool live = c < Nc;
-            const int64_t srow = ((int64_t)c * Ny + y) * N;
+            float2* bb = buf + (((int64_t)e * Nc + cb) * Ny + y) * N;   // block-uniform
+            const float2* cm = S.coils + ((int64_t)cb * Ny + y) * N;
+            const uint32_t o = tau * cstride + p;
             float2 a[N1];
 #pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1) {
-                const int z = p + N2 * n1;
-                a[n1] = live ? fft_cmul(ld2(S.coils, srow + z), U[z]) : make_float2(0.f, 0.f);
-            }
+            for (int n1 = 0; n1 < N1; ++n1)
+                a[n1] = live ? fft_cmul(ld2u(cm, o + N2 * n1), U[p + N2 * n1])
+                             : make_float2(0.f, 0.f);
             fft_team<LOGZ, false>(a, p, Tt, Geo::RS, 1, tw);
             if (live) {
-                const int64_t crow = (((int64_t)e * Nc + c) * Ny + y) * N;
 #pragma unroll
                 for (int n1 = 0; n1 < N1; ++n1)
-                    buf[crow + p + N2 * n1] = make_float2(a[n1].x * sc, a[n1].y * sc);
+                    bb[o + N2 * n1] = make_float2(a[n1].x * sc, a[n1].y * sc);
             }
         }
     }
