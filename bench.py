@@ -256,6 +256,34 @@ def copy_leg(torch, mib=256, reps=3):
     return dict(bytes_read=n * 4, bytes_written=n * 4, launches=reps)
 
 
+def bandwidth(torch):
+    """Achievable HBM bandwidth with plain torch kernels (copy, sum, axpy) on
+    256 MiB and 1 GiB float32 arrays, GB/s of the bytes each must move: the
+    practical ceiling next to the 8 TB/s peak."""
+    dev = torch.device("cuda:0")
+    res = {}
+    for mib in (256, 1024):
+        n = mib * 2 ** 20 // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        for name, fn, nbytes in [("copy", lambda: b.copy_(a), 2 * n * 4),
+                                 ("sum", lambda: a.sum(), n * 4),
+                                 ("axpy", lambda: b.add_(a, alpha=0.5), 3 * n * 4)]:
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            res[f"{name}_{mib}MiB_GBs"] = round(nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9)
+        del a, b
+    print(json.dumps({"bandwidth": res}))
+
+
 def sweep(g, torch, repeats=10):
     """Throughput against volume size (cf. the paper's scaling figure): for each
     model and N in {1e2, 1e3, 1e4, 1e5, 2.5e5, 1e6} voxels, the median wall
@@ -428,6 +456,56 @@ def cpu_baseline(sample_vox=6144, gpu_moments=None):
     return out, err
 
 
+def adam_oracle_error(g, torch, side=16):
+    """The Adam+TV workload's recipe on a side^3 volume (TV couples voxels, so
+    a cut-out of the 64^3 run would be another problem): GPU against the FP64
+    oracle on the same FP32 data, same hyper-parameters."""
+    import oracle
+    from paper_2511_22094_amd import synth
+    d = synth.cfg2(shape=(side, side, side))
+    kw = synth.CFG2_ADAM
+    y = synth.scatter((oracle.forward("dwi2", d.acq, d.truth) + d.sigma * d.noise)
+                      .astype(np.float32), d.mask)
+    names = synth.PARAM_NAMES["dwi2"]
+    tvp = tuple(names.index(p) for p in kw["tv_params"])
+    m = g.Model.from_acq("dwi2", d.acq)
+    out = g.gc_fit_askadam(m, y, d.mask, d.lb, d.ub, n_iter=kw["n_iter"], loss=kw["loss"],
+                           lam=kw["lam"], tv_params=tvp, tv_dim=kw["tv_dim"], loss_history=True)
+    ref = oracle.askadam("dwi2", d.acq, d.mask, y, d.lb, d.ub, n_iter=kw["n_iter"],
+                         loss=kw["loss"], lam=kw["lam"], tv_mask=sum(1 << p for p in tvp),
+                         tv_dim=kw["tv_dim"], n_threads=min(os.cpu_count() or 1, 16))
+    err = np.abs(out["maps"] - ref["maps"]) / (d.ub - d.lb)[:, None, None, None]
+    return {"what": f"|GPU - oracle| / (ub - lb) of the 5 maps after {kw['n_iter']} Adam "
+                    f"iterations with 3D TV on a {side}^3 volume of the same recipe",
+            "median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
+            "max": float(err.max()),
+            "final_loss_rel": float(abs(out["loss"][-1] / ref["loss"][-1] - 1))}
+
+
+def sense_oracle_error(g, E=6, Nc=8, Ny=64, Nz=64):
+    """The reconstruction workload's hyper-parameters on a smaller slice: GPU
+    against the FP64 oracle on the same FP32 data."""
+    from oracle import sense
+    from paper_2511_22094_amd import synth
+    kw = synth.SENSE_RECON
+    d = synth.sense_draw(43, E, Nc, Ny, Nz, sigma=kw["sigma"])
+    k = ((sense.forward(d.truth, d.coils) + d.sigma * d.noise) * d.mask[:, None]).astype(np.complex64)
+    C = d.coils.astype(np.complex64)
+    out = g.gc_sense_recon(k, C, d.mask, lr=kw["lr"], n_iter=kw["n_iter"], loss=kw["loss"],
+                           lam=kw["lam"], loss_history=True)
+    img, hist = sense.recon(k.astype(complex), C.astype(complex), d.mask, n_iter=kw["n_iter"],
+                            lr=kw["lr"], loss=kw["loss"], lam=kw["lam"])
+    err = np.abs(out["image"] - img) / np.abs(img).max()
+    rel = np.abs(out["loss"] / hist - 1)
+    return {"what": f"|GPU - oracle| / max|I| of the image after {kw['n_iter']} iterations "
+                    f"(L1 + TV, {E} echoes x {Nc} coils, {Ny}x{Nz}); L1 residual signs at "
+                    "the rounding level let FP32 and FP64 trajectories part, so the loss "
+                    "histories are the sharper comparison",
+            "median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
+            "max": float(err.max()), "loss_rel_max": float(rel.max()),
+            "final_loss_rel": float(rel[-1])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -439,6 +517,8 @@ def main():
     ap.add_argument("--no-sense", action="store_true")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving leg on the full 256-job trace (voxels up to 1e6)")
+    ap.add_argument("--bandwidth", action="store_true",
+                    help="achievable HBM bandwidth of plain torch kernels (no headline line)")
     ap.add_argument("--sweep", action="store_true",
                     help="throughput against volume size per model (no headline line)")
     ap.add_argument("--profile-only", default=None,
@@ -454,6 +534,9 @@ def main():
     g = lib()
     if args.sweep:
         sweep(g, torch)
+        return
+    if args.bandwidth:
+        bandwidth(torch)
         return
     if args.profile_only:
         legs = [x.strip() for x in args.profile_only.split(",") if x.strip()]
@@ -494,11 +577,19 @@ def main():
     serve = None
     if not args.no_serve:
         serve = serve_leg(g, torch, args.serve_full)
-    cpu = oracle_err = None
+    cpu = oracle_err = adam_err = sense_err = None
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         cpu, oracle_err = cpu_baseline(gpu_moments=mh["moments"])
         log(f"bench: CPU {cpu['value']:.3e} voxel-iter/s on {cpu['cores']} threads")
+        if adam is not None:
+            log("bench: Adam+TV error against the oracle (16^3)")
+            adam_err = adam_oracle_error(g, torch)
+            log(f"bench:   {adam_err}")
+        if sense is not None:
+            log("bench: reconstruction error against the oracle (6 x 8 x 64 x 64)")
+            sense_err = sense_oracle_error(g)
+            log(f"bench:   {sense_err}")
     out = {
         "metric": "voxel-iterations/sec (MCMC MH & Adam steps) at 1 GPU",
         "value": mh["value"],
@@ -522,6 +613,7 @@ def main():
                      "flop_per_step": FLOP_PER_MH_STEP_GRE3,
                      "launch_ms": mh["per_launch_ms"]},
         "cpu_baseline": cpu,
+        "speedup_vs_cpu_oracle": (mh["value"] / cpu["value"]) if cpu else None,
         "oracle_error": oracle_err,
     }
     if adam is not None:
@@ -534,7 +626,8 @@ def main():
                                     "unit": "GB/s", "frac": adam["achieved_gbs"] / PEAK_HBM_GBS,
                                     "traffic": measured_traffic("fit_step"),
                                     "bytes_per_voxel_iter": BYTES_PER_ADAM_TV_VOXEL_ITER,
-                                    "launch_us": adam["per_launch_us"]}}
+                                    "launch_us": adam["per_launch_us"]},
+                       "oracle_error": adam_err}
     if sense is not None:
         dom = max(sense["stages"], key=lambda k: sense["stages"][k]["launch_us"])
         st = sense["stages"][dom]
@@ -549,7 +642,8 @@ def main():
                                      "unit": "GB/s", "frac": st["achieved_gbs"] / PEAK_HBM_GBS,
                                      "traffic": measured_traffic(dom),
                                      "bytes_per_launch": st["bytes"],
-                                     "launch_us": st["launch_us"]}}
+                                     "launch_us": st["launch_us"]},
+                        "oracle_error": sense_err}
     if serve is not None:
         out["serving"] = serve
     print(json.dumps(out))
