@@ -19,7 +19,8 @@ Readings (where the paper is silent):
     of the real and of the imaginary part of every echo image, scaled by
     lambda / Npix, Npix = E Ny Nz;
   * the unknowns are Re I and Im I, unbounded (no projection), start 0;
-  * Adam as for the parameter fits (FP64 here), learning rate in image units.
+  * Adam, SGDM and RMSProp as for the parameter fits (FP64 here), learning
+    rate in image units.
 """
 from __future__ import annotations
 
@@ -76,8 +77,12 @@ def loss_grad(img, coils, mask, k, loss=2, lam=0.0):
 
 
 def recon(k, coils, mask, n_iter=100, lr=0.01, loss=2, lam=0.0, beta1=0.9, beta2=0.999,
-          eps=1e-8, init=None):
-    """askadam on Re I and Im I from I = 0 (or init); returns (image, loss history)."""
+          eps=1e-8, init=None, optimizer="adam", momentum=0.9, rho=0.9):
+    """askadam on Re I and Im I from I = 0 (or init); returns (image, loss history).
+
+    optimizer "adam" | "sgdm" | "rmsprop", with the update rules of the
+    parameter fits: SGDM vel = momentum vel - lr g, I += vel; RMSProp
+    v = rho v + (1 - rho) g^2, I -= lr g / (sqrt(v) + eps)."""
     E, Ny, Nz = mask.shape
     img = np.zeros((E, Ny, Nz), complex) if init is None else np.array(init, complex)
     m = np.zeros((2, E, Ny, Nz))
@@ -87,10 +92,19 @@ def recon(k, coils, mask, n_iter=100, lr=0.01, loss=2, lam=0.0, beta1=0.9, beta2
         L, g = loss_grad(img, coils, mask, k, loss, lam)
         hist.append(L)
         gg = np.stack([g.real, g.imag])
-        m = beta1 * m + (1 - beta1) * gg
-        v = beta2 * v + (1 - beta2) * gg * gg
-        c1 = 1.0 / (1.0 - beta1 ** t)
-        c2 = 1.0 / (1.0 - beta2 ** t)
-        step = lr * (m * c1) / (np.sqrt(v * c2) + eps)
+        if optimizer == "adam":
+            m = beta1 * m + (1 - beta1) * gg
+            v = beta2 * v + (1 - beta2) * gg * gg
+            c1 = 1.0 / (1.0 - beta1 ** t)
+            c2 = 1.0 / (1.0 - beta2 ** t)
+            step = lr * (m * c1) / (np.sqrt(v * c2) + eps)
+        elif optimizer == "sgdm":
+            m = momentum * m - lr * gg
+            step = -m
+        elif optimizer == "rmsprop":
+            v = rho * v + (1 - rho) * gg * gg
+            step = lr * gg / (np.sqrt(v) + eps)
+        else:
+            raise ValueError(optimizer)
         img = (img.real - step[0]) + 1j * (img.imag - step[1])
     return img, np.array(hist)

@@ -156,6 +156,25 @@ def test_adam_recon_matches_oracle(loss, lam, T):
         assert np.mean(err > 1e-4) < 0.02 and err.max() < 0.1
 
 
+@pytest.mark.parametrize("opt,kw", [("sgdm", dict(lr=1000.0, momentum=0.8)),
+                                    ("rmsprop", dict(lr=0.003, rho=0.9))])
+def test_sgdm_and_rmsprop_recon_match_oracle(opt, kw):
+    """The other two optimisers of the parameter fits, L2, 40 iterations."""
+    d = _draw((3, 4, 64, 32), 8)
+    k = _kspace(d).astype(np.complex64)
+    C = d.coils.astype(np.complex64)
+    init = _start(d)
+    out = G().gc_sense_recon(k, C, d.mask, init=init, optimizer=opt, n_iter=40, loss=2,
+                             loss_history=True, **kw)
+    img, hist = sense.recon(k.astype(complex), C.astype(complex), d.mask, n_iter=40, loss=2,
+                            init=init.astype(complex), optimizer=opt, **kw)
+    err = np.abs(out["image"] - img) / np.abs(img).max()
+    say(opt, "recon |dI| median", np.median(err), "max", err.max())
+    np.testing.assert_allclose(out["loss"], hist, rtol=1e-5)
+    # RMSProp divides by |g| like Adam (components with g near 0 step by rounding)
+    assert np.median(err) < 1e-6 and err.max() < (2e-3 if opt == "rmsprop" else 1e-5)
+
+
 def test_l1_tv_recon_loss_follows_oracle():
     """L1 + TV over 30 iterations: past the point where one echo's trajectory
     parts (see above) the losses still agree to 1e-3 (the FP32 emulation on

@@ -86,3 +86,49 @@ def test_single_coil_full_sampling_converges_to_inverse_dft():
     # Adam with a fixed rate ends within a few of its steps of the minimiser
     np.testing.assert_allclose(img, truth, atol=2e-3)
     assert np.median(np.abs(img - truth)) < 1e-4
+
+
+def _ls_problem(seed):
+    """One unit coil, full sampling, L2: A^H A = 1, so the gradient is
+    (2 / Nk) (I - I*) with I* = F2^H k, and every real component of the error
+    follows its own scalar recurrence."""
+    rng = np.random.default_rng(seed)
+    E, Ny, Nz = 1, 8, 8
+    truth = _rand((E, Ny, Nz), rng)
+    C = np.ones((1, Ny, Nz), complex)
+    mask = np.ones((E, Ny, Nz), bool)
+    k = sense.forward(truth, C)
+    h = 2.0 / (2.0 * mask.sum())          # curvature 2 / Nk, Nk = 2 Nc |M|
+    return truth, C, mask, k, h
+
+
+def test_sgdm_follows_the_heavy_ball_recurrence():
+    truth, C, mask, k, h = _ls_problem(6)
+    lr, mu, T = 40.0, 0.7, 25
+    img, _ = sense.recon(k, C, mask, n_iter=T, lr=lr, optimizer="sgdm", momentum=mu)
+    # error e = I - I*, velocity w: w <- mu w - lr h e; e <- e + w (from I = 0: e0 = -I*)
+    e, w = -truth.copy(), np.zeros_like(truth)
+    for _ in range(T):
+        w = mu * w - lr * h * e
+        e = e + w
+    np.testing.assert_allclose(img - truth, e, rtol=1e-9, atol=1e-12)
+    # the recurrence's characteristic roots bound the decay: |e_T| <= C rho^T
+    assert np.abs(e).max() < np.abs(truth).max()
+
+
+def test_rmsprop_follows_its_scalar_recurrence():
+    truth, C, mask, k, h = _ls_problem(7)
+    lr, rho, eps, T = 0.05, 0.9, 1e-8, 30
+    img, _ = sense.recon(k, C, mask, n_iter=T, lr=lr, optimizer="rmsprop", rho=rho, eps=eps)
+    for idx in [(0, 0, 0), (0, 3, 5), (0, 7, 7)]:
+        for part, get in ((0, np.real), (1, np.imag)):
+            e = -float(get(truth[idx]))
+            v = 0.0
+            for _ in range(T):
+                g = h * e
+                v = rho * v + (1 - rho) * g * g
+                e = e - lr * g / (np.sqrt(v) + eps)
+            got = float(get(img[idx] - truth[idx]))
+            # RMSProp divides by |g|: the transforms' 1e-16 rounding of the
+            # gradient, relative to |e| ~ 1e-4, adds up to ~1e-12 over the steps
+            assert got == pytest.approx(e, rel=1e-9, abs=1e-11), (idx, part)
