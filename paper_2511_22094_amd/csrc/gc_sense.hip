@@ -100,75 +100,86 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
     __shared__ float red[4];
     if (stop && stop[0] != 0) return;   // uniform
     const int nzg = S.Nz / G;
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int ec = blk / nzg, z0 = (blk % nzg) * G;
-    const int e = ec / S.Nc, c = ec % S.Nc;
     const int t = threadIdx.x, j = t % G, p = t / G;
     float2* tw = lds;
     float2* T = lds + N + j;
-    for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twy, i);
-    __syncthreads();
     const uint32_t Nz = S.Nz;
-    const int z = z0 + j;
-    const int64_t img = (int64_t)ec * S.Ny * Nz;            // this coil image (block-uniform)
-    float2* bimg = buf + img;                               // element (y, z) at y Nz + z
-    const uint32_t bit = 1u << j;
-    const int64_t tile = (int64_t)e * nzg + z0 / G;
-    const uint32_t* ti = S.tinfo + tile * S.Ny;              // row y of this tile at ti[y]
+    const int64_t isz = (int64_t)S.Ny * Nz;                  // one coil image
+    const int tl = xcd_block(blockIdx.x, gridDim.x);          // tile: (e, c, z / G)
     float2 a[N1];
-    if (MODE == 2) {
+    {
+        const int ec = tl / nzg, z0 = (tl % nzg) * G;
+        const int e = ec / S.Nc, c = ec % S.Nc;
+        const int z = z0 + j;
+        const int64_t img = (int64_t)ec * isz;                // this coil image (block-uniform)
+        float2* bimg = buf + img;                             // element (y, z) at y Nz + z
+        const uint32_t bit = 1u << j;
+        const int64_t tile = (int64_t)e * nzg + z0 / G;
+        const uint32_t* ti = S.tinfo + tile * S.Ny;           // row y of this tile at ti[y]
+        // the tile's columns, row masks and (iterating) measured samples are
+        // fetched up front, without branches, so that the loads overlap
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) {
-            const int y = p + N2 * n1;
-            a[n1] = (gload(ti)[y] & bit) ? ld2u(in + img, y * Nz + z) : make_float2(0.f, 0.f);
+        for (int n1 = 0; n1 < N1; ++n1)
+            a[n1] = ld2u(MODE == 2 ? in + img : bimg, (p + N2 * n1) * Nz + z);
+        uint32_t word[N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) word[n1] = gload(ti)[p + N2 * n1];
+        float2 kv[N1];
+        if (MODE == 0) {
+            const float2* kc = S.kc + (int64_t)c * S.S + gload(S.tbase)[tile];
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) {   // unsampled entries read sample 0 and drop it
+                const uint32_t s = (word[n1] & bit) ? (word[n1] >> 16) + __popc(word[n1] & (bit - 1u)) : 0u;
+                kv[n1] = ld2u(kc, s);
+            }
         }
-    } else {
+        // twiddles to LDS while the column loads are in flight
+        for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twy, i);
+        __syncthreads();
+        if (MODE == 2) {
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) a[n1] = ld2u(bimg, (p + N2 * n1) * Nz + z);
-        fft_team<LOGY, false>(a, p, T, Geo::RS, G, tw);
-    }
-    const float sc = S.rsqrtNy;
-    if (MODE == 1) {
-#pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) {
-            const int y = p + N2 * n1;
-            const bool smp = (gload(ti)[y] & bit) != 0;
-            out[img + y * Nz + z] =
-                smp ? make_float2(a[n1].x * sc, a[n1].y * sc) : make_float2(0.f, 0.f);
+            for (int n1 = 0; n1 < N1; ++n1)
+                if (!(word[n1] & bit)) a[n1] = make_float2(0.f, 0.f);
+        } else {
+            fft_team<LOGY, false>(a, p, T, Geo::RS, G, tw);
         }
-        return;
-    }
-    float lsum = 0.f;
-    if (MODE == 0) {
-        const float2* kc = S.kc + (int64_t)c * S.S + gload(S.tbase)[tile];
-        const float sd = S.scale_data;
+        const float sc = S.rsqrtNy;
+        if (MODE == 1) {
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) {
-            const int y = p + N2 * n1;
-            const uint32_t word = gload(ti)[y];
-            float2 d = make_float2(0.f, 0.f);
-            if (word & bit) {
-                const int s = (int)(word >> 16) + __popc(word & (bit - 1u));
-                const float2 k = ld2u(kc, (uint32_t)s);
-                const float rx = a[n1].x * sc - k.x, ry = a[n1].y * sc - k.y;
-                if (S.loss_p == 2) {
-                    lsum += rx * rx + ry * ry;
-                    d = make_float2(2.f * rx * sd, 2.f * ry * sd);
-                } else {
-                    lsum += fabsf(rx) + fabsf(ry);
-                    d = make_float2(sgnf(rx) * sd, sgnf(ry) * sd);
+            for (int n1 = 0; n1 < N1; ++n1) {
+                const int y = p + N2 * n1;
+                out[img + y * Nz + z] = (word[n1] & bit) ? make_float2(a[n1].x * sc, a[n1].y * sc)
+                                                        : make_float2(0.f, 0.f);
+            }
+        } else {
+            float lsum = 0.f;
+            if (MODE == 0) {
+                const float sd = S.scale_data;
+#pragma unroll
+                for (int n1 = 0; n1 < N1; ++n1) {
+                    float2 d = make_float2(0.f, 0.f);
+                    if (word[n1] & bit) {
+                        const float rx = a[n1].x * sc - kv[n1].x, ry = a[n1].y * sc - kv[n1].y;
+                        if (S.loss_p == 2) {
+                            lsum += rx * rx + ry * ry;
+                            d = make_float2(2.f * rx * sd, 2.f * ry * sd);
+                        } else {
+                            lsum += fabsf(rx) + fabsf(ry);
+                            d = make_float2(sgnf(rx) * sd, sgnf(ry) * sd);
+                        }
+                    }
+                    a[n1] = d;
                 }
             }
-            a[n1] = d;
-        }
-    }
-    fft_team<LOGY, true>(a, p, T, Geo::RS, G, tw);
+            fft_team<LOGY, true>(a, p, T, Geo::RS, G, tw);
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1)
-        bimg[(p + N2 * n1) * Nz + z] = make_float2(a[n1].x * sc, a[n1].y * sc);
-    if (MODE == 0 && partial) {
-        const float s = block_sum_pow2(lsum * S.scale_data, red);
-        if (t == 0) partial[blockIdx.x] = s;
+            for (int n1 = 0; n1 < N1; ++n1)
+                bimg[(p + N2 * n1) * Nz + z] = make_float2(a[n1].x * sc, a[n1].y * sc);
+            if (MODE == 0 && partial) {
+                const float s = block_sum_pow2(lsum * S.scale_data, red);
+                if (t == 0) partial[tl] = s;
+            }
+        }
     }
 }
 
@@ -177,8 +188,11 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
 //         with fwd, the next iteration's forward rows into buf)
 // MODE 1: operator head (forward rows of img_in into buf)
 // MODE 2: adjoint tail (sum over coils of conj(C_c) F_z^H(buf), to out)
+// 256-point rows run best at 4 waves per SIMD (measured; 8 bytes of spill);
+// other lengths keep the registers the compiler wants.
 template <int LOGZ, int MODE>
-__global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LOGZ == 8 ? 4 : 1)))
+void sense_zrows_kernel(SenseDev S, SenseOpt O,
                                                          const float2* __restrict__ img_in,
                                                          float2* __restrict__ img_out,
                                                          float2* __restrict__ m,
@@ -201,9 +215,31 @@ __global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O
     float2* U = lds + N;
     float2* T = lds + 2 * N;
     float2* Tt = T + tau * Geo::AREA;
-    for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twz, i);
     const int64_t row = ((int64_t)e * Ny + y) * N;   // image row (e, y), block-uniform
     const uint32_t cstride = (uint32_t)Ny * N;        // coil to coil within buf and the maps
+    // A batch is TEAMS coil rows.  Teams past the last coil read the last
+    // coil's row and drop it, so that every load is unconditional and all of
+    // them overlap.
+    float2 a[N1], cv[N1];
+    auto load_batch = [&](int cb) {
+        const int c = cb + tau;
+        const float2* bb = buf + (((int64_t)e * Nc + cb) * Ny + y) * N;   // block-uniform
+        const float2* cm = S.coils + ((int64_t)cb * Ny + y) * N;
+        const uint32_t o = (uint32_t)((c < Nc ? c : Nc - 1) - cb) * cstride + p;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            a[n1] = ld2u(bb, o + N2 * n1);
+            cv[n1] = ld2u(cm, o + N2 * n1);
+        }
+    };
+    float2 twv[(N + Geo::THREADS - 1) / Geo::THREADS];   // twiddles: loads issued first
+#pragma unroll
+    for (int k = 0; k * Geo::THREADS < N; ++k)
+        twv[k] = ld2(S.twz, min(t + k * Geo::THREADS, N - 1));
+    if (MODE != 1) load_batch(0);   // in flight while the twiddles are staged
+#pragma unroll
+    for (int k = 0; k * Geo::THREADS < N; ++k)
+        if (t + k * Geo::THREADS < N) tw[t + k * Geo::THREADS] = twv[k];
     if (MODE == 1)
         for (int z = t; z < N; z += Geo::THREADS) U[z] = ld2u(img_in + row, z);
     __syncthreads();
@@ -214,23 +250,14 @@ __global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) acc[n1] = make_float2(0.f, 0.f);
         for (int cb = 0; cb < Nc; cb += TEAMS) {   // uniform trip count (barriers inside)
-            const int c = cb + tau;
-            const bool live = c < Nc;
-            const float2* bb = buf + (((int64_t)e * Nc + cb) * Ny + y) * N;   // block-uniform
-            const float2* cm = S.coils + ((int64_t)cb * Ny + y) * N;
-            const uint32_t o = tau * cstride + p;
-            float2 a[N1];
-#pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1)
-                a[n1] = live ? ld2u(bb, o + N2 * n1) : make_float2(0.f, 0.f);
+            if (cb > 0) load_batch(cb);
+            const bool live = cb + tau < Nc;
             fft_team<LOGZ, true>(a, p, Tt, Geo::RS, 1, tw);
-            if (live) {
 #pragma unroll
-                for (int n1 = 0; n1 < N1; ++n1) {
-                    const float2 q = cmulc(a[n1], ld2u(cm, o + N2 * n1));
-                    acc[n1].x += q.x;
-                    acc[n1].y += q.y;
-                }
+            for (int n1 = 0; n1 < N1; ++n1) {
+                const float2 q = cmulc(a[n1], cv[n1]);
+                acc[n1].x += live ? q.x : 0.f;
+                acc[n1].y += live ? q.y : 0.f;
             }
         }
         __syncthreads();   // every team is done with its transpose area
@@ -253,29 +280,21 @@ __global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O
             const float2* irow = img_in + row;
             const float2 u = ld2u(irow, z);
             if (O.scale_tv != 0.f) {
-                float gx = 0.f, gy = 0.f, R = 0.f;
-                if (z + 1 < N) {   // forward neighbours: pairs (u, q)
-                    const float2 q = ld2u(irow, z + 1);
-                    R += fabsf(q.x - u.x) + fabsf(q.y - u.y);
-                    gx -= sgnf(q.x - u.x);
-                    gy -= sgnf(q.y - u.y);
-                }
-                if (y + 1 < Ny) {
-                    const float2 q = ld2u(irow + N, z);
-                    R += fabsf(q.x - u.x) + fabsf(q.y - u.y);
-                    gx -= sgnf(q.x - u.x);
-                    gy -= sgnf(q.y - u.y);
-                }
-                if (z > 0) {       // backward neighbours: pairs (q, u)
-                    const float2 q = ld2u(irow, z - 1);
-                    gx += sgnf(u.x - q.x);
-                    gy += sgnf(u.y - q.y);
-                }
-                if (y > 0) {
-                    const float2 q = ld2u(irow - N, z);
-                    gx += sgnf(u.x - q.x);
-                    gy += sgnf(u.y - q.y);
-                }
+                // neighbours read at clamped positions (a pixel on the border
+                // reads itself: difference 0, and its pair does not count)
+                const bool zf = z + 1 < N, yf = y + 1 < Ny, zb = z > 0, yb = y > 0;
+                const float2 qzf = ld2u(irow, zf ? z + 1 : z);
+                const float2 qyf = ld2u(irow + (yf ? N : 0), z);
+                const float2 qzb = ld2u(irow, zb ? z - 1 : z);
+                const float2 qyb = ld2u(irow - (yb ? N : 0), z);
+                // forward pairs (u, q): |q - u| counts, -sign(q - u) on u
+                const float R = (zf ? fabsf(qzf.x - u.x) + fabsf(qzf.y - u.y) : 0.f) +
+                                (yf ? fabsf(qyf.x - u.x) + fabsf(qyf.y - u.y) : 0.f);
+                // backward pairs (q, u): +sign(u - q) on u; sign(0) = 0 covers the borders
+                const float gx = sgnf(u.x - qzb.x) + sgnf(u.x - qyb.x) - sgnf(qzf.x - u.x) -
+                                 sgnf(qyf.x - u.x);
+                const float gy = sgnf(u.y - qzb.y) + sgnf(u.y - qyb.y) - sgnf(qzf.y - u.y) -
+                                 sgnf(qyf.y - u.y);
                 g.x += O.scale_tv * gx;
                 g.y += O.scale_tv * gy;
                 tvl += O.scale_tv * R;
@@ -313,12 +332,12 @@ __global__ __launch_bounds__(256) void sense_zrows_kernel(SenseDev S, SenseOpt O
             const bool live = c < Nc;
             float2* bb = buf + (((int64_t)e * Nc + cb) * Ny + y) * N;   // block-uniform
             const float2* cm = S.coils + ((int64_t)cb * Ny + y) * N;
-            const uint32_t o = tau * cstride + p;
+            const uint32_t o = (uint32_t)((live ? c : Nc - 1) - cb) * cstride + p;
             float2 a[N1];
 #pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1)
-                a[n1] = live ? fft_cmul(ld2u(cm, o + N2 * n1), U[p + N2 * n1])
-                             : make_float2(0.f, 0.f);
+            for (int n1 = 0; n1 < N1; ++n1) a[n1] = ld2u(cm, o + N2 * n1);
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) a[n1] = fft_cmul(a[n1], U[p + N2 * n1]);
             fft_team<LOGZ, false>(a, p, Tt, Geo::RS, 1, tw);
             if (live) {
 #pragma unroll
