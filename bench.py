@@ -68,12 +68,12 @@ MEASURED_TRAFFIC = {
         "read_bytes": 126873332, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "6d1e4f4e726910a13bece9e9eb3b2d820d307c346fc19cdb1d0078bf4af9525b",
-        "read_bytes": 112491638, "write_bytes": 100663501,
+        "sha256": "5903b57a787cb87d1727484c9d4874731156e97a237a9ce88667e3e5d8e7fd4e",
+        "read_bytes": 112252895, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "6d1e4f4e726910a13bece9e9eb3b2d820d307c346fc19cdb1d0078bf4af9525b",
-        "read_bytes": 142073075, "write_bytes": 109899252,
+        "sha256": "5903b57a787cb87d1727484c9d4874731156e97a237a9ce88667e3e5d8e7fd4e",
+        "read_bytes": 148150079, "write_bytes": 111472118,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
