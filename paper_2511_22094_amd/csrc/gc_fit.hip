@@ -125,19 +125,24 @@ __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f
 // Anisotropic grid TV at voxel v for one map up (iterate t-1): the pairs
 // (v, forward neighbour) add |difference| to R; the subgradient collects the
 // pairs in which v takes part.  nb = (x-, x+, y-, y+, z-, z+), -1 = none.
+// Neighbour values are read unconditionally (a missing neighbour, index -1,
+// reads element 0 and is then ignored) so that all reads of a voxel are in
+// flight together instead of one conditional read waiting after another.
 __device__ __forceinline__ float tv_aniso_at(const float* __restrict__ up, float uv,
                                              const int32_t (&nb)[6], float& R) {
+    float un[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) un[d] = gload(up)[nb[d] >= 0 ? nb[d] : 0];
     float g = 0.f;
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
-        if (nb[d] < 0) continue;
-        const float un = up[nb[d]];
+        const bool in = nb[d] >= 0;
         if (d & 1) {          // forward neighbour: pair (v, nb)
-            const float diff = un - uv;
+            const float diff = in ? un[d] - uv : 0.f;
             R += fabsf(diff);
             g -= sgnf(diff);
         } else {              // backward neighbour: pair (nb, v)
-            g += sgnf(uv - un);
+            g += in ? sgnf(uv - un[d]) : 0.f;
         }
     }
     return g;
@@ -151,10 +156,19 @@ __device__ __forceinline__ float tv_aniso_at(const float* __restrict__ up, float
 __device__ __forceinline__ float tv_iso_at(const float* __restrict__ up, float uv,
                                            const int32_t (&nb)[6], const int32_t (&dg)[3][3],
                                            float& R) {
+    // all neighbour values first (unconditional reads, see tv_aniso_at)
+    float uf[3], ubk[3], ud[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        uf[d] = gload(up)[nb[2 * d + 1] >= 0 ? nb[2 * d + 1] : 0];
+        ubk[d] = gload(up)[nb[2 * d] >= 0 ? nb[2 * d] : 0];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) ud[d][e] = gload(up)[dg[d][e] >= 0 ? dg[d][e] : 0];
+    }
     float D[3], ss = 0.f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        D[d] = nb[2 * d + 1] >= 0 ? up[nb[2 * d + 1]] - uv : 0.f;
+        D[d] = nb[2 * d + 1] >= 0 ? uf[d] - uv : 0.f;
         ss += D[d] * D[d];
     }
     const float Gv = sqrtf(ss);
@@ -166,9 +180,8 @@ __device__ __forceinline__ float tv_iso_at(const float* __restrict__ up, float u
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int32_t b = nb[2 * d];
-        if (b < 0) continue;
-        const float ub = up[b];
+        if (nb[2 * d] < 0) continue;
+        const float ub = ubk[d];
         const float Dv = uv - ub;
         float sb = 0.f;
 #pragma unroll
@@ -176,7 +189,7 @@ __device__ __forceinline__ float tv_iso_at(const float* __restrict__ up, float u
             if (e == d) {
                 sb += Dv * Dv;
             } else if (dg[d][e] >= 0) {
-                const float t = up[dg[d][e]] - ub;
+                const float t = ud[d][e] - ub;
                 sb += t * t;
             }
         }
@@ -381,23 +394,25 @@ __global__ __launch_bounds__(kBlock) void fit_step_kernel(const FitJob* __restri
         float u[P], m[P], s2[P], gu[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            u[p] = J.u_in[(int64_t)p * n + v];
-            m[p] = J.m[(int64_t)p * n + v];
-            s2[p] = J.v[(int64_t)p * n + v];
+            u[p] = gload(J.u_in)[(int64_t)p * n + v];
+            m[p] = gload(J.m)[(int64_t)p * n + v];
+            s2[p] = gload(J.v)[(int64_t)p * n + v];
         }
-        const float w = J.w ? J.w[v] : 1.f;
+        const float w = J.w ? gload(J.w)[v] : 1.f;
         const bool grid_tv = J.tv_mask && J.tv_kind != 2;
         int32_t nb[6], dg[3][3];
         if (grid_tv) {
 #pragma unroll
-            for (int d = 0; d < 6; ++d) nb[d] = J.nbr[(int64_t)d * n + v];
+            for (int d = 0; d < 6; ++d) nb[d] = gload(J.nbr)[(int64_t)d * n + v];
             if (J.tv_kind == 1) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
 #pragma unroll
-                    for (int e = 0; e < 3; ++e)
-                        dg[d][e] = (e != d && nb[2 * d] >= 0)
-                                       ? J.nbr[(int64_t)(2 * e + 1) * n + nb[2 * d]] : -1;
+                    for (int e = 0; e < 3; ++e) {
+                        const int32_t x = gload(J.nbr)[(int64_t)(2 * e + 1) * n +
+                                                       (nb[2 * d] >= 0 ? nb[2 * d] : 0)];
+                        dg[d][e] = (e != d && nb[2 * d] >= 0) ? x : -1;
+                    }
             }
         }
         const YGlob yg{J.y, n, v, J.acq.M};
@@ -421,8 +436,8 @@ __global__ __launch_bounds__(kBlock) void fit_step_kernel(const FitJob* __restri
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const bool on = (J.prior_mask >> p) & 1u;
-                pmu[p] = on ? J.mu[(int64_t)p * n + v] : 0.f;
-                psg[p] = on ? J.sigma[(int64_t)p * n + v] : 1.f;
+                pmu[p] = on ? gload(J.mu)[(int64_t)p * n + v] : 0.f;
+                psg[p] = on ? gload(J.sigma)[(int64_t)p * n + v] : 1.f;
             }
             contrib += prior_at<P>(J, u, pmu, psg, gu);
         }
