@@ -243,6 +243,132 @@ def sense_leg(g, torch, steps, warmup):
                 final_loss=r["final_loss"], rel_err=err)
 
 
+# Algorithmic FP32 operations of one gre3 ensemble (stretch-move) walker step:
+# the likelihood of the MH step (pool set-up 51, 24 echoes x 28, scale 1 = 724),
+# the stretch z = ((a-1)u + 1)^2 / a (4), the proposal theta_j + z (theta_k -
+# theta_j) over 9 parameters (27) and the acceptance (P-1) log z + dlogL (4).
+FLOP_PER_ENS_STEP_GRE3 = 724 + 4 + 27 + 4   # = 759
+
+
+def grid_csr(shape):
+    """6-neighbourhood adjacency of a fully masked grid as CSR (vertex = voxel in
+    grid order, neighbours in the order -x, +x, -y, +y, -z, +z)."""
+    nz, ny, nx = shape
+    g = np.arange(nz * ny * nx, dtype=np.int64).reshape(nz, ny, nx)
+    src, dst = [], []
+    for axis, step in ((2, -1), (2, 1), (1, -1), (1, 1), (0, -1), (0, 1)):
+        a = np.roll(g, -step, axis=axis)
+        ok = np.ones(g.shape, bool)
+        idx = [slice(None)] * 3
+        idx[axis] = -1 if step == 1 else 0
+        ok[tuple(idx)] = False
+        src.append(g[ok])
+        dst.append(a[ok])
+    src = np.concatenate(src)
+    dst = np.concatenate(dst)
+    order = np.argsort(src, kind="stable")
+    rowptr = np.concatenate([[0], np.cumsum(np.bincount(src, minlength=g.size))]).astype(np.int64)
+    return rowptr, dst[order].astype(np.int32)
+
+
+def next_rows_leg(g, torch):
+    """One timed run each of the rows built beyond the main path: the affine-
+    invariant ensemble sampler (50 walkers x 1,800 iterations, thin 100, gre3 on
+    a 128x128x8 slab of the GRE volume), Adam with isotropic TV, SGDM and
+    RMSProp with TV, graph (mesh) TV and the Eq. 6 prior on the 64^3 diffusion
+    workload (500 iterations each).  Kernel times from HIP events."""
+    from paper_2511_22094_amd import synth
+    dev = torch.device("cuda:0")
+    out = {}
+    # ---------------------------------------------------------- ensemble
+    d = synth.cfg1(shape=(8, 128, 128))
+    m = g.Model.from_acq("gre3", d.acq)
+    nz, ny, nx = d.shape
+    s_ = g.gc_model_forward(m, torch.tensor(d.truth, dtype=torch.float32, device=dev))
+    y = (s_ + d.sigma * torch.from_numpy(d.noise).to(dev)).reshape(48, nz, ny, nx).contiguous()
+    mean = torch.empty((9, nz, ny, nx), dtype=torch.float64, device=dev)
+    std = torch.empty_like(mean)
+    W, T = 50, 1800
+
+    def ens():
+        return g.gc_mcmc(m, y, None, d.lb, d.ub, 1, T, 0, 100, sigma=d.sigma, seed=1,
+                         sampler="ensemble", n_walkers=W, stretch=2.0, accept=False,
+                         out_mean=mean, out_std=std)
+
+    ens()
+    torch.cuda.synchronize()
+    g.gc_timing_reset()
+    g.gc_timing_enable(True)
+    t0 = time.perf_counter()
+    ens()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    g.gc_timing_enable(False)
+    kms, nl = g.gc_timing_get("ens_chunk")
+    units = d.n * W * T
+    per = kms / 1e3 / max(nl, 1)
+    tf = FLOP_PER_ENS_STEP_GRE3 * (units / max(nl, 1)) / per / 1e12
+    out["f1_ensemble"] = {
+        "value": units / sec, "unit": "voxel-walker-iterations/s", "sec": sec,
+        "workload": f"gre3, {d.n} voxels (128x128x8), {W} walkers x {T} iterations, thin 100",
+        "roofline": {"bound": "alu", "kernel": "ens_chunk<gre3>", "achieved": tf,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS,
+                     "flop_per_step": FLOP_PER_ENS_STEP_GRE3, "launch_ms": per * 1e3}}
+    del y, s_, mean, std
+    # ------------------------------------------------ fit-step variants
+    d = synth.cfg2()
+    kw = synth.CFG2_ADAM
+    m = g.Model.from_acq("dwi2", d.acq)
+    nz, ny, nx = d.shape
+    s_ = g.gc_model_forward(m, torch.tensor(d.truth, dtype=torch.float32, device=dev))
+    y = (s_ + d.sigma * torch.from_numpy(d.noise).to(dev)).reshape(96, nz, ny, nx).contiguous()
+    maps = torch.empty((5, nz, ny, nx), dtype=torch.float32, device=dev)
+    tvp = tuple(synth.PARAM_NAMES["dwi2"].index(p) for p in kw["tv_params"])
+    rowptr, col = grid_csr(d.shape)
+    rng = np.random.default_rng(5)
+    rngp = (d.ub - d.lb)[:, None, None, None]
+    mu = torch.from_numpy((d.lb[:, None, None, None] + rngp * rng.uniform(0.3, 0.7, (5,) + d.shape))
+                          .astype(np.float32)).to(dev)
+    sg = torch.from_numpy((rngp * rng.uniform(0.05, 0.2, (5,) + d.shape)).astype(np.float32)).to(dev)
+    base = dict(n_iter=kw["n_iter"], loss=kw["loss"], lam=kw["lam"], tv_params=tvp,
+                tv_dim=kw["tv_dim"], out=maps)
+    variants = [
+        ("f2_adam_iso_tv", dict(base, tv_kind="iso"), 528 + 36,
+         "Adam, isotropic 3D TV (+ 9 neighbour-table reads per voxel)"),
+        ("f2_sgdm_tv", dict(base, optimizer="sgdm", lr=0.05), 528 - 40,
+         "SGDM (momentum 0.9, lr 0.05), anisotropic 3D TV (one state array)"),
+        ("f2_rmsprop_tv", dict(base, optimizer="rmsprop", lr=0.002), 528 - 40,
+         "RMSProp (rho 0.9, lr 0.002), anisotropic 3D TV (one state array)"),
+        ("f3_graph_tv", dict(base, tv_kind="graph", graph=(torch.from_numpy(rowptr).to(dev),
+                                                           torch.from_numpy(col).to(dev))),
+         528 - 24 + 8 + 24, "Adam, graph TV on the 6-neighbourhood mesh of the grid (CSR)"),
+        ("f3_prior", dict(base, prior_lam=0.02, prior_params=(0, 1, 2), prior_mu=mu,
+                          prior_sigma=sg), 528 + 24, "Adam, 3D TV and the Eq. 6 prior on f, Da, De"),
+    ]
+    for name, kwv, bpv, what in variants:
+        def fit():
+            return g.gc_fit_askadam(m, y, None, d.lb, d.ub, **kwv)
+        fit()
+        torch.cuda.synchronize()
+        g.gc_timing_reset()
+        g.gc_timing_enable(True, every=10)
+        t0 = time.perf_counter()
+        r = fit()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        g.gc_timing_enable(False)
+        kms, nl = g.gc_timing_get("fit_step")
+        per = kms / 1e3 / max(nl, 1)
+        gbs = bpv * d.n / per / 1e9
+        out[name] = {"value": d.n * kw["n_iter"] / sec, "unit": "voxel-iterations/s",
+                     "workload": f"dwi2 64^3, 500 iterations; {what}",
+                     "final_loss": r["final_loss"],
+                     "roofline": {"bound": "hbm", "kernel": "fit_step<dwi2>", "achieved": gbs,
+                                  "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                                  "bytes_per_voxel_iter": bpv, "launch_us": per * 1e6}}
+    return out
+
+
 def copy_leg(torch, mib=256, reps=3):
     """A plain device copy of known size (mib MiB read + mib MiB written per launch): the
     calibration launch for the HBM byte counters."""
@@ -515,6 +641,8 @@ def main():
     ap.add_argument("--no-adam", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-sense", action="store_true")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the ensemble / optimiser / regulariser legs")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving leg on the full 256-job trace (voxels up to 1e6)")
     ap.add_argument("--bandwidth", action="store_true",
@@ -574,6 +702,12 @@ def main():
         sense = sense_leg(g, torch, args.steps, args.warmup)
         log(f"bench: reconstruction {sense['value']:.1f} iterations/s, "
             + ", ".join(f"{k} {v['launch_us']:.1f} us" for k, v in sense["stages"].items()))
+    nxt = None
+    if not args.no_next:
+        log("bench: next-row legs (ensemble, optimisers, regularisers)")
+        nxt = next_rows_leg(g, torch)
+        for k, v in nxt.items():
+            log(f"bench:   {k}: {v['value']:.3e} {v['unit']}, frac {v['roofline']['frac']:.3f}")
     serve = None
     if not args.no_serve:
         serve = serve_leg(g, torch, args.serve_full)
@@ -644,6 +778,8 @@ def main():
                                      "bytes_per_launch": st["bytes"],
                                      "launch_us": st["launch_us"]},
                         "oracle_error": sense_err}
+    if nxt is not None:
+        out["next_rows"] = nxt
     if serve is not None:
         out["serving"] = serve
     print(json.dumps(out))
