@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 # (E, Nc, Ny, Nz)
 SHAPES = [(2, 3, 32, 16), (1, 2, 2, 16), (3, 4, 64, 32), (1, 2, 1024, 16), (1, 1, 16, 1024),
-          (2, 2, 512, 64)]
+          (2, 2, 512, 64), (2, 20, 64, 256)]   # last: a second, partial batch of coil rows
 
 
 def _draw(shape, seed, sigma=0.01):
@@ -88,7 +88,7 @@ def test_full_slice_operators_match_oracle():
 
 
 @pytest.mark.parametrize("loss,lam", [(2, 0.0), (1, 0.0), (2, 0.5), (1, 0.5)])
-@pytest.mark.parametrize("shape", [(2, 3, 32, 16), (1, 2, 512, 64)])
+@pytest.mark.parametrize("shape", [(2, 3, 32, 16), (1, 2, 512, 64), (2, 20, 32, 256)])
 def test_one_step_gradient_matches_oracle(loss, lam, shape):
     """SGDM with momentum 0: (init - image) / lr = dL/dRe + i dL/dIm, and the
     recorded loss is the loss at init.  The rate makes lr |g| about 100 |init|
