@@ -40,10 +40,11 @@ sys.path.insert(0, ROOT)
 #   proposal 9 x FMA                                   18
 #   Box-Muller 5 pairs x (log, mul, sqrt, sin, cos, 2 mul)   35
 #   acceptance log, subtract                            2
-#   per pool set-up: rcp, 2 x (2 mul, exp, sin, cos, 2 mul), amplitude 2 mul   3 x 17 = 51
+#   per pool set-up: rcp, one complex step factor q = exp(-dTE/T2 + i 2 pi df dTE)
+#     (2 mul, exp, sin, cos, 2 mul) and the first echo z = A q (2 mul)   3 x 10 = 30
 #   per echo: 3 complex updates (4 mul + 2 add) + 4 adds + 2 sub + 2 FMA: 28 x 24 = 672
 #   likelihood scale                                    1
-FLOP_PER_MH_STEP_GRE3 = 18 + 35 + 2 + 51 + 672 + 1      # = 779
+FLOP_PER_MH_STEP_GRE3 = 18 + 35 + 2 + 30 + 672 + 1      # = 758
 # Algorithmic HBM bytes per voxel-iteration of the dwi2 Adam+TV step kernel:
 #   data 96 x 4, iterate 5 x 4 in + out, Adam m, v 2 x 5 x 4 in + out,
 #   neighbour table 6 x 4 (neighbour iterate values are re-reads of the

@@ -380,10 +380,15 @@ template <typename R> struct Gre3 {
             R zr[3], zi[3], qr[3], qi[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                cexp(kr[k] * te0, kp[k] * te0, zr[k], zi[k]);
-                zr[k] *= th[k];
-                zi[k] *= th[k];
                 cexp(kr[k] * dte, kp[k] * dte, qr[k], qi[k]);
+                if (te0 == dte) {   // first echo one step after TE = 0: z = A q
+                    zr[k] = th[k] * qr[k];
+                    zi[k] = th[k] * qi[k];
+                } else {
+                    cexp(kr[k] * te0, kp[k] * te0, zr[k], zi[k]);
+                    zr[k] *= th[k];
+                    zi[k] *= th[k];
+                }
             }
             GC_FOR_MEAS(m, MAXM, a.M) {
                 R sr = zr[0] + zr[1] + zr[2];
@@ -431,8 +436,13 @@ template <typename R> struct Gre3 {
             R te0 = AcqView<R>::te0(a), dte = AcqView<R>::dte(a);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                cexp(kr[k] * te0, kp[k] * te0, ur[k], ui[k]);
                 cexp(kr[k] * dte, kp[k] * dte, qr[k], qi[k]);
+                if (te0 == dte) {   // first echo one step after TE = 0: u = q
+                    ur[k] = qr[k];
+                    ui[k] = qi[k];
+                } else {
+                    cexp(kr[k] * te0, kp[k] * te0, ur[k], ui[k]);
+                }
             }
         }
         GC_FOR_MEAS(m, MAXM, a.M) {
