@@ -318,8 +318,10 @@ int gc_tv_graph(int64_t n, const int64_t *rowptr, const int32_t *col, int64_t nn
  * Complex arrays are interleaved (re, im) floats.  Ny and Nz are powers of
  * two, 2 <= Ny <= 1024, 16 <= Nz <= 1024, and 1 <= n_echo, n_coil <= 1024
  * (GC_E_INVAL otherwise; also for a reconstruction whose mask samples
- * nothing).  Working memory: about 8 E Nc Ny Nz + 32 E Ny Nz bytes of device
- * memory per call, released before return.
+ * nothing).  Working memory per call, released before return: the coil-image
+ * buffer 8 E Nc Ny Nz bytes, image, Adam state and loss terms about
+ * 32 E Ny Nz bytes, the measured samples 8 Nc S bytes (S sampled entries)
+ * and, for host (GC_MEM_HOST) arguments, device copies of the inputs.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int ny, nz, n_echo, n_coil;
