@@ -32,8 +32,17 @@ ACQS = {
 
 @pytest.mark.parametrize("model", list(ACQS))
 def test_forward_and_vjp_match_oracle(orc, model):
+    _forward_and_vjp(orc, model, ACQS[model])
+
+
+def test_gre3_echoes_offset_from_spacing_match_oracle(orc):
+    """First echo at 3 ms, spacing 2 ms: the echo recurrence starts from its
+    own first-echo term instead of one step factor."""
+    _forward_and_vjp(orc, "gre3", synth.Acq(te=synth.echo_times(3.0, 2.0, 24)))
+
+
+def _forward_and_vjp(orc, model, acq):
     g = G()
-    acq = ACQS[model]
     m = g.Model.from_acq(model, acq)
     n = 3000   # several blocks and a ragged tail
     th = _theta(model, n, 1)

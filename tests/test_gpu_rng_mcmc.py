@@ -83,6 +83,21 @@ def _small(model, shape, seed, sigma, mask_frac=0.8):
 ])
 def test_mh_fp64_bit_exact(orc, model, shape, sigma, kw):
     d = synth.cfg0() if model == "monoexp_t2s" else _small(model, shape, 5, sigma)
+    _mh_fp64_bit_exact(orc, d, model, shape, kw)
+
+
+def test_mh_fp64_bit_exact_gre3_offset_echoes(orc):
+    """gre3 with the first echo at 3 ms and 2 ms spacing (the recurrence's
+    other start)."""
+    rng = np.random.default_rng(104)
+    shape = (3, 6, 5)
+    mask = (rng.uniform(size=shape) < 0.8).astype(np.uint8)
+    d = synth.make_draw("gre3", shape, 5, 0.01, acq=synth.Acq(te=synth.echo_times(3.0, 2.0, 24)),
+                        mask=mask)
+    _mh_fp64_bit_exact(orc, d, "gre3", shape, dict(n_chains=4, n_iter=400, burnin=100, thin=10))
+
+
+def _mh_fp64_bit_exact(orc, d, model, shape, kw):
     y, yg = _data(orc, d)
     step = synth.MH_STEP[model]
     say("mh fp64", model, shape, kw)
