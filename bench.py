@@ -370,6 +370,70 @@ def next_rows_leg(g, torch):
     return out
 
 
+def next_rows_oracle_error(g, torch):
+    """The next-row legs against the FP64 oracle on small problems of the same
+    recipes: the ensemble on 512 voxels of the GRE slab (same random streams,
+    each side's own forward model for the data), in units of the oracle's
+    posterior SD; each fit variant on a 16^3 volume of the diffusion recipe,
+    |GPU - oracle| / (ub - lb) of the maps."""
+    import oracle
+    from paper_2511_22094_amd import synth
+    threads = min(os.cpu_count() or 1, 16)
+    out = {}
+    d = synth.cfg1(shape=(8, 128, 128))
+    idx = np.sort(np.random.default_rng(77).choice(d.n, 512, replace=False))
+    W, T = 50, 1800
+    y = (oracle.forward("gre3", d.acq, d.truth[:, idx]) + d.sigma * d.noise[:, idx]).astype(np.float32)
+    ref = oracle.ensemble("gre3", d.acq, y, d.lb, d.ub, d.sigma, 1, W, T, 0, 100, stretch=2.0,
+                          n_threads=threads)
+    m = g.Model.from_acq("gre3", d.acq)
+    r = g.gc_mcmc(m, y.reshape(48, 1, 1, idx.size), None, d.lb, d.ub, 1, T, 0, 100,
+                  sigma=d.sigma, seed=1, sampler="ensemble", n_walkers=W, stretch=2.0,
+                  accept=False)
+    sd = np.maximum(ref["std"], 1e-300)
+    dm = np.abs(r["mean"].reshape(9, -1) - ref["mean"]) / sd
+    ds = np.abs(r["std"].reshape(9, -1) - ref["std"]) / sd
+    out["f1_ensemble"] = {"what": "|GPU - oracle| of posterior mean / SD in units of the oracle's "
+                                  "SD, 512 voxels x 9 parameters, FP32 vs FP64 walkers",
+                          "mean_median": float(np.median(dm)), "mean_p99": float(np.quantile(dm, 0.99)),
+                          "sd_median": float(np.median(ds)), "sd_p99": float(np.quantile(ds, 0.99))}
+    d = synth.cfg2(shape=(16, 16, 16))
+    kw = synth.CFG2_ADAM
+    y = synth.scatter((oracle.forward("dwi2", d.acq, d.truth) + d.sigma * d.noise)
+                      .astype(np.float32), d.mask)
+    m = g.Model.from_acq("dwi2", d.acq)
+    tvp = tuple(synth.PARAM_NAMES["dwi2"].index(p) for p in kw["tv_params"])
+    tvm = sum(1 << p for p in tvp)
+    rowptr, col = grid_csr(d.shape)
+    rng = np.random.default_rng(5)
+    rngp = (d.ub - d.lb)[:, None, None, None]
+    mu = (d.lb[:, None, None, None] + rngp * rng.uniform(0.3, 0.7, (5,) + d.shape)).astype(np.float32)
+    sg = (rngp * rng.uniform(0.05, 0.2, (5,) + d.shape)).astype(np.float32)
+    base_g = dict(n_iter=kw["n_iter"], loss=kw["loss"], lam=kw["lam"], tv_params=tvp,
+                  tv_dim=kw["tv_dim"])
+    base_o = dict(n_iter=kw["n_iter"], loss=kw["loss"], lam=kw["lam"], tv_mask=tvm,
+                  tv_dim=kw["tv_dim"], n_threads=threads)
+    cases = [
+        ("f2_adam_iso_tv", dict(tv_kind="iso"), dict(tv_kind="iso")),
+        ("f2_sgdm_tv", dict(optimizer="sgdm", lr=0.05), dict(optimizer="sgdm", lr=0.05)),
+        ("f2_rmsprop_tv", dict(optimizer="rmsprop", lr=0.002), dict(optimizer="rmsprop", lr=0.002)),
+        ("f3_graph_tv", dict(tv_kind="graph", graph=(rowptr, col)),
+         dict(tv_kind="graph", graph=(rowptr, col))),
+        ("f3_prior", dict(prior_lam=0.02, prior_params=(0, 1, 2), prior_mu=mu, prior_sigma=sg),
+         dict(prior_lam=0.02, prior_mask=0b111, prior_mu=mu.astype(np.float64),
+              prior_sigma=sg.astype(np.float64))),
+    ]
+    for name, kg, ko in cases:
+        r = g.gc_fit_askadam(m, y, d.mask, d.lb, d.ub, loss_history=True, **base_g, **kg)
+        ref = oracle.askadam("dwi2", d.acq, d.mask, y, d.lb, d.ub, **base_o, **ko)
+        err = np.abs(r["maps"] - ref["maps"]) / rngp
+        out[name] = {"what": "|GPU - oracle| / (ub - lb) of the maps, 16^3 volume, 500 iterations",
+                     "median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
+                     "max": float(err.max()),
+                     "final_loss_rel": float(abs(r["loss"][-1] / ref["loss"][-1] - 1))}
+    return out
+
+
 def copy_leg(torch, mib=256, reps=3):
     """A plain device copy of known size (mib MiB read + mib MiB written per launch): the
     calibration launch for the HBM byte counters."""
@@ -721,6 +785,11 @@ def main():
             log("bench: Adam+TV error against the oracle (16^3)")
             adam_err = adam_oracle_error(g, torch)
             log(f"bench:   {adam_err}")
+        if nxt is not None:
+            log("bench: next-row errors against the oracle")
+            for k, v in next_rows_oracle_error(g, torch).items():
+                nxt[k]["oracle_error"] = v
+                log(f"bench:   {k}: {v}")
         if sense is not None:
             log("bench: reconstruction error against the oracle (6 x 8 x 64 x 64)")
             sense_err = sense_oracle_error(g)
