@@ -49,9 +49,32 @@ class TotalVariation(torch.autograd.Function):
         return dR * gR.to(dR.dtype), None, None
 
 
+class SenseOperator(torch.autograd.Function):
+    """k = M_e F2(C_c I_e) of the reconstruction (paper §2.6.4, Eq. 7) for a
+    complex64 image [E, Ny, Nz] (gc_sense_forward); backward applies the
+    adjoint sum_c conj(C_c) F2^H(M_e dk) (gc_sense_adjoint), which for torch's
+    complex gradients (dL/dRe + i dL/dIm) is the vector-Jacobian product."""
+
+    @staticmethod
+    def forward(ctx, image: torch.Tensor, coils: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
+        g = _load()
+        ctx.save_for_backward(coils, mask)
+        return g.gc_sense_forward(image.contiguous(), coils, mask)
+
+    @staticmethod
+    def backward(ctx, dk: torch.Tensor):
+        g = _load()
+        coils, mask = ctx.saved_tensors
+        return g.gc_sense_adjoint(dk.contiguous(), coils, mask), None, None
+
+
 def forward_model(theta: torch.Tensor, model) -> torch.Tensor:
     return ForwardModel.apply(theta, model)
 
 
 def total_variation(u: torch.Tensor, mask=None, tv_dim: int = 3) -> torch.Tensor:
     return TotalVariation.apply(u, mask, tv_dim)
+
+
+def sense_operator(image: torch.Tensor, coils: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
+    return SenseOperator.apply(image, coils, mask)

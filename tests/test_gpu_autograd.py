@@ -61,3 +61,31 @@ def test_autograd_tv(orc):
     Rr, dRr = orc.tv(mask, u.detach().double().cpu().numpy(), 3, 3.0)
     assert R.item() == pytest.approx(Rr, rel=1e-6)
     assert np.array_equal(u.grad.cpu().numpy(), dRr.astype(np.float32))
+
+
+def test_autograd_through_the_reconstruction_operator():
+    """A torch L2 data term on the HIP operator: autograd's image gradient (via
+    the HIP adjoint) equals the oracle's analytic gradient of the same loss."""
+    import torch
+    from oracle import sense
+    from paper_2511_22094_amd.autograd import sense_operator
+    d = synth.sense_draw(7, 3, 8, 64, 32, sigma=0.01)
+    k = ((sense.forward(d.truth, d.coils) + d.sigma * d.noise) * d.mask[:, None]).astype(np.complex64)
+    C = d.coils.astype(np.complex64)
+    rng = np.random.default_rng(8)
+    img0 = (d.truth + 0.1 * (rng.standard_normal(d.truth.shape) +
+                             1j * rng.standard_normal(d.truth.shape))).astype(np.complex64)
+    Nk = 2.0 * C.shape[0] * d.mask.sum()
+    x = torch.tensor(img0, device="cuda", requires_grad=True)
+    Ct = torch.from_numpy(C).cuda()
+    Mt = torch.from_numpy(d.mask).cuda()
+    kt = torch.from_numpy(k).cuda()
+    r = sense_operator(x, Ct, Mt) - kt
+    loss = (r.real ** 2 + r.imag ** 2).sum() / Nk
+    loss.backward()
+    L, gref = sense.loss_grad(img0.astype(complex), C.astype(complex), d.mask, k.astype(complex), 2)
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-5)
+    gt = x.grad.cpu().numpy()
+    err = np.abs(gt - gref).max() / np.abs(gref).max()
+    say("reconstruction operator autograd vs oracle gradient", err)
+    assert err < 2e-5
