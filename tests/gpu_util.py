@@ -15,7 +15,7 @@ def gpu_available() -> bool:
 
 
 def G():
-    """The HIP binding; on a GPU machine a missing library is an error, not a skip."""
+    """The HIP binding; where a GPU is present a missing library is an error, not a skip."""
     from paper_2511_22094_amd import lib
     return lib()
 
