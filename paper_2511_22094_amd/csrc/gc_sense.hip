@@ -107,78 +107,76 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
     const int64_t isz = (int64_t)S.Ny * Nz;                  // one coil image
     const int tl = xcd_block(blockIdx.x, gridDim.x);          // tile: (e, c, z / G)
     float2 a[N1];
-    {
-        const int ec = tl / nzg, z0 = (tl % nzg) * G;
-        const int e = ec / S.Nc, c = ec % S.Nc;
-        const int z = z0 + j;
-        const int64_t img = (int64_t)ec * isz;                // this coil image (block-uniform)
-        float2* bimg = buf + img;                             // element (y, z) at y Nz + z
-        const uint32_t bit = 1u << j;
-        const int64_t tile = (int64_t)e * nzg + z0 / G;
-        const uint32_t* ti = S.tinfo + tile * S.Ny;           // row y of this tile at ti[y]
-        // the tile's columns, row masks and (iterating) measured samples are
-        // fetched up front, without branches, so that the loads overlap
+    const int ec = tl / nzg, z0 = (tl % nzg) * G;
+    const int e = ec / S.Nc, c = ec % S.Nc;
+    const int z = z0 + j;
+    const int64_t img = (int64_t)ec * isz;                // this coil image (block-uniform)
+    float2* bimg = buf + img;                             // element (y, z) at y Nz + z
+    const uint32_t bit = 1u << j;
+    const int64_t tile = (int64_t)e * nzg + z0 / G;
+    const uint32_t* ti = S.tinfo + tile * S.Ny;           // row y of this tile at ti[y]
+    // the tile's columns, row masks and (iterating) measured samples are
+    // fetched up front, without branches, so that the loads overlap
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1)
+        a[n1] = ld2u(MODE == 2 ? in + img : bimg, (p + N2 * n1) * Nz + z);
+    uint32_t word[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) word[n1] = gload(ti)[p + N2 * n1];
+    float2 kv[N1];
+    if (MODE == 0) {
+        const float2* kc = S.kc + (int64_t)c * S.S + gload(S.tbase)[tile];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {   // unsampled entries read sample 0 and drop it
+            const uint32_t s = (word[n1] & bit) ? (word[n1] >> 16) + __popc(word[n1] & (bit - 1u)) : 0u;
+            kv[n1] = ld2u(kc, s);
+        }
+    }
+    // twiddles to LDS while the column loads are in flight
+    for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twy, i);
+    __syncthreads();
+    if (MODE == 2) {
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1)
-            a[n1] = ld2u(MODE == 2 ? in + img : bimg, (p + N2 * n1) * Nz + z);
-        uint32_t word[N1];
+            if (!(word[n1] & bit)) a[n1] = make_float2(0.f, 0.f);
+    } else {
+        fft_team<LOGY, false>(a, p, T, Geo::RS, G, tw);
+    }
+    const float sc = S.rsqrtNy;
+    if (MODE == 1) {
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) word[n1] = gload(ti)[p + N2 * n1];
-        float2 kv[N1];
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int y = p + N2 * n1;
+            out[img + y * Nz + z] = (word[n1] & bit) ? make_float2(a[n1].x * sc, a[n1].y * sc)
+                                                    : make_float2(0.f, 0.f);
+        }
+    } else {
+        float lsum = 0.f;
         if (MODE == 0) {
-            const float2* kc = S.kc + (int64_t)c * S.S + gload(S.tbase)[tile];
-#pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1) {   // unsampled entries read sample 0 and drop it
-                const uint32_t s = (word[n1] & bit) ? (word[n1] >> 16) + __popc(word[n1] & (bit - 1u)) : 0u;
-                kv[n1] = ld2u(kc, s);
-            }
-        }
-        // twiddles to LDS while the column loads are in flight
-        for (int i = t; i < N; i += Geo::THREADS) tw[i] = ld2(S.twy, i);
-        __syncthreads();
-        if (MODE == 2) {
-#pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1)
-                if (!(word[n1] & bit)) a[n1] = make_float2(0.f, 0.f);
-        } else {
-            fft_team<LOGY, false>(a, p, T, Geo::RS, G, tw);
-        }
-        const float sc = S.rsqrtNy;
-        if (MODE == 1) {
+            const float sd = S.scale_data;
 #pragma unroll
             for (int n1 = 0; n1 < N1; ++n1) {
-                const int y = p + N2 * n1;
-                out[img + y * Nz + z] = (word[n1] & bit) ? make_float2(a[n1].x * sc, a[n1].y * sc)
-                                                        : make_float2(0.f, 0.f);
-            }
-        } else {
-            float lsum = 0.f;
-            if (MODE == 0) {
-                const float sd = S.scale_data;
-#pragma unroll
-                for (int n1 = 0; n1 < N1; ++n1) {
-                    float2 d = make_float2(0.f, 0.f);
-                    if (word[n1] & bit) {
-                        const float rx = a[n1].x * sc - kv[n1].x, ry = a[n1].y * sc - kv[n1].y;
-                        if (S.loss_p == 2) {
-                            lsum += rx * rx + ry * ry;
-                            d = make_float2(2.f * rx * sd, 2.f * ry * sd);
-                        } else {
-                            lsum += fabsf(rx) + fabsf(ry);
-                            d = make_float2(sgnf(rx) * sd, sgnf(ry) * sd);
-                        }
+                float2 d = make_float2(0.f, 0.f);
+                if (word[n1] & bit) {
+                    const float rx = a[n1].x * sc - kv[n1].x, ry = a[n1].y * sc - kv[n1].y;
+                    if (S.loss_p == 2) {
+                        lsum += rx * rx + ry * ry;
+                        d = make_float2(2.f * rx * sd, 2.f * ry * sd);
+                    } else {
+                        lsum += fabsf(rx) + fabsf(ry);
+                        d = make_float2(sgnf(rx) * sd, sgnf(ry) * sd);
                     }
-                    a[n1] = d;
                 }
+                a[n1] = d;
             }
-            fft_team<LOGY, true>(a, p, T, Geo::RS, G, tw);
+        }
+        fft_team<LOGY, true>(a, p, T, Geo::RS, G, tw);
 #pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1)
-                bimg[(p + N2 * n1) * Nz + z] = make_float2(a[n1].x * sc, a[n1].y * sc);
-            if (MODE == 0 && partial) {
-                const float s = block_sum_pow2(lsum * S.scale_data, red);
-                if (t == 0) partial[tl] = s;
-            }
+        for (int n1 = 0; n1 < N1; ++n1)
+            bimg[(p + N2 * n1) * Nz + z] = make_float2(a[n1].x * sc, a[n1].y * sc);
+        if (MODE == 0 && partial) {
+            const float s = block_sum_pow2(lsum * S.scale_data, red);
+            if (t == 0) partial[tl] = s;
         }
     }
 }
