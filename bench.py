@@ -69,11 +69,11 @@ MEASURED_TRAFFIC = {
         "read_bytes": 127183942, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "324c9687a7677e3ca849c7eda2ef11e641a0e554a270755001847125055eb834",
+        "sha256": "8b6e1a2433ae7f670e2e138d1bfa59c76ecf0176ab470ea904902336ea03f0c6",
         "read_bytes": 112252498, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "324c9687a7677e3ca849c7eda2ef11e641a0e554a270755001847125055eb834",
+        "sha256": "8b6e1a2433ae7f670e2e138d1bfa59c76ecf0176ab470ea904902336ea03f0c6",
         "read_bytes": 148140395, "write_bytes": 111472118,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
