@@ -1,0 +1,41 @@
+"""Host-side helpers that need no GPU: the bench's mesh adjacency and the
+synthetic reconstruction inputs."""
+import numpy as np
+
+from graphs import grid_graph
+from paper_2511_22094_amd import synth
+
+
+def test_bench_grid_csr_is_the_six_neighbourhood_graph():
+    import bench
+    shape = (3, 4, 5)
+    rp, col = bench.grid_csr(shape)
+    r2, c2 = grid_graph(np.ones(shape, np.uint8), 3)
+    assert np.array_equal(rp, r2)
+    for i in range(rp.size - 1):
+        assert sorted(col[rp[i]:rp[i + 1]]) == sorted(c2[r2[i]:r2[i + 1]])
+    # symmetric, no self loops
+    pairs = {(i, int(j)) for i in range(rp.size - 1) for j in col[rp[i]:rp[i + 1]]}
+    assert all((j, i) in pairs for i, j in pairs) and all(i != j for i, j in pairs)
+
+
+def test_caipi_mask_pattern():
+    """R_y = 1, R_z = 9, z-shift 3 per line, TE-shift 2 per echo."""
+    m = synth.caipi_mask(6, 27, 36)
+    assert m.dtype == np.uint8 and m.shape == (6, 27, 36)
+    # every line samples every ninth z position
+    assert np.all(m.sum(axis=2) == 36 // 9)
+    for e in range(6):
+        for y in range(27):
+            z = np.flatnonzero(m[e, y])
+            assert np.all(np.diff(z) == 9) and (z[0] - 3 * y - 2 * e) % 9 == 0
+    assert m.mean() == 1 / 9
+
+
+def test_sense_draw_is_seeded_and_shaped():
+    a = synth.sense_draw(3, 2, 4, 16, 32)
+    b = synth.sense_draw(3, 2, 4, 16, 32)
+    assert a.truth.shape == (2, 16, 32) and a.coils.shape == (4, 16, 32)
+    assert a.noise.shape == (2, 4, 16, 32) and a.mask.shape == (2, 16, 32)
+    assert np.array_equal(a.truth, b.truth) and np.array_equal(a.noise, b.noise)
+    assert np.abs(a.coils).max() <= 1.0 + 1e-12
