@@ -448,12 +448,14 @@ def copy_leg(torch, mib=256, reps=3):
 
 
 def bandwidth(torch):
-    """Achievable HBM bandwidth with plain torch kernels (copy, sum, axpy) on
-    256 MiB and 1 GiB float32 arrays, GB/s of the bytes each must move: the
-    practical ceiling next to the 8 TB/s peak."""
+    """Achievable bandwidth with plain torch kernels (copy, sum, axpy) on
+    float32 arrays of 32 MiB to 1 GiB, GB/s of the bytes each must move, each
+    kernel repeated back to back: the practical ceiling next to the 8 TB/s
+    HBM peak.  Working sets up to a few hundred MiB can stay in the 256 MB
+    Infinity Cache between repetitions; 1 GiB arrays cannot."""
     dev = torch.device("cuda:0")
     res = {}
-    for mib in (256, 1024):
+    for mib in (32, 64, 128, 256, 1024):
         n = mib * 2 ** 20 // 4
         a = torch.ones(n, device=dev)
         b = torch.empty_like(a)
