@@ -120,6 +120,51 @@ def _mh_fp64_bit_exact(orc, d, model, shape, kw):
     assert np.all(out["mean"][:, d.mask == 0] == 0) and np.all(out["accept"][:, d.mask == 0] == 0)
 
 
+@pytest.mark.parametrize("model,te", [
+    ("gre3", [2, 3.5, 5, 7, 9, 11.5, 14, 17, 20, 23, 26.5, 30, 33, 36.5, 40, 43, 46, 49, 52, 55]),
+    ("gre3", synth.echo_times(3.0, 2.0, 24)),     # 24 registers, recurrence from exp(TE1)
+    ("gre3", synth.echo_times(2.0, 2.0, 20)),     # 20 of 24 registers, guarded
+    ("gre3", synth.echo_times(2.0, 2.0, 24)),     # the straight-line workload form
+    ("monoexp_t2s", synth.echo_times(2.0, 4.0, 10)),
+    ("monoexp_t2s", synth.echo_times(2.0, 3.0, 16)),
+], ids=["gre3-irregular20", "gre3-offset24", "gre3-uniform20", "gre3-uniform24",
+        "mono-10", "mono-16"])
+def test_mh_fp32_register_variants_follow_oracle_chains(orc, model, te):
+    """The FP32 kernels with data in registers (one instantiation per echo
+    count, guarded or straight-line, recurrence or direct) follow the FP64
+    oracle's chains decision for decision wherever the oracle's decisions
+    are far from ties: chains start at the truth, so log-likelihoods are
+    O(M) and their FP32 error (below 1e-3 nats at the 99th percentile for
+    gre3) stays under the 0.005-nat margin required.  Steps are scaled to
+    about a third accepted.  A wrong likelihood would part the chains at
+    once."""
+    rng = np.random.default_rng(77)
+    shape = (3, 8, 10)
+    mask = (rng.uniform(size=shape) < 0.9).astype(np.uint8)
+    d = synth.make_draw(model, shape, 21, 0.01, acq=synth.Acq(te=np.asarray(te, float)),
+                        mask=mask)
+    y, yg = _data(orc, d)
+    C, kw = 2, dict(n_iter=100, burnin=50, thin=5)
+    step = (0.2 if model == "gre3" else 1.0) * np.asarray(synth.MH_STEP[model])
+    x0 = d.truth.astype(np.float32)
+    ref = orc.mh(model, d.acq, y, d.lb, d.ub, step, d.sigma, 13, C,
+                 x0=np.broadcast_to(x0.astype(np.float64), (C,) + x0.shape), **kw)
+    out = G().gc_mcmc(_model(d), yg, d.mask, d.lb, d.ub, C, sigma=d.sigma, step=step, seed=13,
+                      x0_map=synth.scatter(x0, d.mask), x0_mode="given", final_state=True, **kw)
+    far = ref["margin"] > 0.005
+    say("fp32 variants", model, len(te), "far from ties:", far.mean(),
+        "accepted", ref["accept"].mean() / kw["n_iter"])
+    assert far.mean() > 0.6
+    acc = synth.gather(out["accept"], d.mask)
+    assert np.array_equal(acc[:, far], ref["accept"][:, far])
+    rng_ = (d.ub - d.lb)[None, :, None]
+    fin = out["final_state"].reshape(d.n_params, C, d.n).transpose(1, 0, 2)
+    err = np.abs(fin - ref["final"]) / rng_
+    assert err[:, :, far].max() < 1e-4
+    merr = np.abs(synth.gather(out["mean"], d.mask) - ref["mean"]) / rng_[0]
+    assert merr[:, far].max() < 1e-4
+
+
 def test_mh_uniform_init_fp64_bit_exact(orc):
     d = _small("monoexp_t2s", (2, 4, 4), 8, 0.02)
     y, yg = _data(orc, d)
