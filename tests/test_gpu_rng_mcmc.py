@@ -127,11 +127,13 @@ def _mh_fp64_bit_exact(orc, d, model, shape, kw):
     ("gre3", synth.echo_times(2.0, 2.0, 24)),     # the straight-line workload form
     ("monoexp_t2s", synth.echo_times(2.0, 4.0, 10)),
     ("monoexp_t2s", synth.echo_times(2.0, 3.0, 16)),
+    ("linear3", synth.echo_times(2.0, 4.0, 12)),
+    ("dwi2", None),                                # 96 measurements read from memory
 ], ids=["gre3-irregular20", "gre3-offset24", "gre3-uniform20", "gre3-uniform24",
-        "mono-10", "mono-16"])
+        "mono-10", "mono-16", "linear3-12", "dwi2-96"])
 def test_mh_fp32_register_variants_follow_oracle_chains(orc, model, te):
-    """The FP32 kernels with data in registers (one instantiation per echo
-    count, guarded or straight-line, recurrence or direct) follow the FP64
+    """The FP32 kernels (data in registers: one instantiation per echo count,
+    guarded or straight-line, recurrence or direct; dwi2 reads memory) follow the FP64
     oracle's chains decision for decision wherever the oracle's decisions
     are far from ties: chains start at the truth, so log-likelihoods are
     O(M) and their FP32 error (below 1e-3 nats at the 99th percentile for
@@ -141,18 +143,19 @@ def test_mh_fp32_register_variants_follow_oracle_chains(orc, model, te):
     rng = np.random.default_rng(77)
     shape = (3, 8, 10)
     mask = (rng.uniform(size=shape) < 0.9).astype(np.uint8)
-    d = synth.make_draw(model, shape, 21, 0.01, acq=synth.Acq(te=np.asarray(te, float)),
-                        mask=mask)
+    acq = None if te is None else synth.Acq(te=np.asarray(te, float))
+    d = synth.make_draw(model, shape, 21, 0.02 if model == "dwi2" else 0.01, acq=acq, mask=mask)
     y, yg = _data(orc, d)
     C, kw = 2, dict(n_iter=100, burnin=50, thin=5)
-    step = (0.2 if model == "gre3" else 1.0) * np.asarray(synth.MH_STEP[model])
+    scale = {"gre3": 0.2, "dwi2": 0.3, "linear3": 0.3}.get(model, 1.0)
+    step = scale * np.asarray(synth.MH_STEP[model])
     x0 = d.truth.astype(np.float32)
     ref = orc.mh(model, d.acq, y, d.lb, d.ub, step, d.sigma, 13, C,
                  x0=np.broadcast_to(x0.astype(np.float64), (C,) + x0.shape), **kw)
     out = G().gc_mcmc(_model(d), yg, d.mask, d.lb, d.ub, C, sigma=d.sigma, step=step, seed=13,
                       x0_map=synth.scatter(x0, d.mask), x0_mode="given", final_state=True, **kw)
     far = ref["margin"] > 0.005
-    say("fp32 variants", model, len(te), "far from ties:", far.mean(),
+    say("fp32 variants", model, d.acq.n_meas, "far from ties:", far.mean(),
         "accepted", ref["accept"].mean() / kw["n_iter"])
     assert far.mean() > 0.6
     acc = synth.gather(out["accept"], d.mask)
