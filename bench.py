@@ -245,10 +245,10 @@ def sense_leg(g, torch, steps, warmup):
 
 
 # Algorithmic FP32 operations of one gre3 ensemble (stretch-move) walker step:
-# the likelihood of the MH step (pool set-up 51, 24 echoes x 28, scale 1 = 724),
+# the likelihood of the MH step (pool set-up 30, 24 echoes x 28, scale 1 = 703),
 # the stretch z = ((a-1)u + 1)^2 / a (4), the proposal theta_j + z (theta_k -
 # theta_j) over 9 parameters (27) and the acceptance (P-1) log z + dlogL (4).
-FLOP_PER_ENS_STEP_GRE3 = 724 + 4 + 27 + 4   # = 759
+FLOP_PER_ENS_STEP_GRE3 = 703 + 4 + 27 + 4   # = 738
 
 
 def grid_csr(shape):
