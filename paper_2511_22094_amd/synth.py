@@ -423,6 +423,10 @@ def sense_draw(seed: int, n_echo: int = 6, n_coil: int = 32, ny: int = 256, nz: 
 
 # Reconstruction workload: one slice of the paper's multi-echo GRE demo
 # geometry (6 echoes, CAIPI R_z = 9), 32 coils, 256 x 256 phase encodes,
-# L1 data loss with 2D TV (the paper's regularised setting), Adam.
+# L1 data loss with 2D TV, Adam.  The TV weight 0.002 and the 500 iterations
+# are the paper's settings for its regularised reconstruction (Table 1); the
+# rate is not given there, and 0.1 lets 500 iterations reach the TV floor on
+# this phantom's scale (relative error against the phantom 0.18 after 500
+# iterations, 0.16 after 3000; 0.57 at rate 0.01).
 SENSE_RECON = dict(n_echo=6, n_coil=32, ny=256, nz=256, sigma=0.01, n_iter=500, loss=1,
-                   lam=0.05, lr=0.01)
+                   lam=0.002, lr=0.1)
