@@ -272,16 +272,12 @@ def grid_csr(shape):
     return rowptr, dst[order].astype(np.int32)
 
 
-def next_rows_leg(g, torch):
-    """One timed run each of the rows built beyond the main path: the affine-
-    invariant ensemble sampler (50 walkers x 1,800 iterations, thin 100, gre3 on
-    a 128x128x8 slab of the GRE volume), Adam with isotropic TV, SGDM and
-    RMSProp with TV, graph (mesh) TV and the Eq. 6 prior on the 64^3 diffusion
-    workload (500 iterations each).  Kernel times from HIP events."""
+def ens_leg(g, torch, warmup=1):
+    """One timed run of the affine-invariant ensemble sampler: 50 walkers x
+    1,800 iterations, thin 100 (900 retained samples per voxel, as in the
+    paper's ensemble setting), gre3 on a 128x128x8 slab of the GRE volume."""
     from paper_2511_22094_amd import synth
     dev = torch.device("cuda:0")
-    out = {}
-    # ---------------------------------------------------------- ensemble
     d = synth.cfg1(shape=(8, 128, 128))
     m = g.Model.from_acq("gre3", d.acq)
     nz, ny, nx = d.shape
@@ -296,7 +292,8 @@ def next_rows_leg(g, torch):
                          sampler="ensemble", n_walkers=W, stretch=2.0, accept=False,
                          out_mean=mean, out_std=std)
 
-    ens()
+    for _ in range(warmup):
+        ens()
     torch.cuda.synchronize()
     g.gc_timing_reset()
     g.gc_timing_enable(True)
@@ -309,13 +306,25 @@ def next_rows_leg(g, torch):
     units = d.n * W * T
     per = kms / 1e3 / max(nl, 1)
     tf = FLOP_PER_ENS_STEP_GRE3 * (units / max(nl, 1)) / per / 1e12
-    out["f1_ensemble"] = {
+    return {
         "value": units / sec, "unit": "voxel-walker-iterations/s", "sec": sec,
         "workload": f"gre3, {d.n} voxels (128x128x8), {W} walkers x {T} iterations, thin 100",
         "roofline": {"bound": "alu", "kernel": "ens_chunk<gre3>", "achieved": tf,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS,
                      "flop_per_step": FLOP_PER_ENS_STEP_GRE3, "launch_ms": per * 1e3}}
-    del y, s_, mean, std
+
+
+def next_rows_leg(g, torch):
+    """One timed run each of the rows built beyond the main path: the affine-
+    invariant ensemble sampler (50 walkers x 1,800 iterations, thin 100, gre3 on
+    a 128x128x8 slab of the GRE volume), Adam with isotropic TV, SGDM and
+    RMSProp with TV, graph (mesh) TV and the Eq. 6 prior on the 64^3 diffusion
+    workload (500 iterations each).  Kernel times from HIP events."""
+    from paper_2511_22094_amd import synth
+    dev = torch.device("cuda:0")
+    out = {}
+    # ---------------------------------------------------------- ensemble
+    out["f1_ensemble"] = ens_leg(g, torch, warmup=1)
     # ------------------------------------------------ fit-step variants
     d = synth.cfg2()
     kw = synth.CFG2_ADAM
@@ -717,7 +726,7 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="throughput against volume size per model (no headline line)")
     ap.add_argument("--profile-only", default=None,
-                    help="comma list of mh, adam, copy: run only these legs once each (no "
+                    help="comma list of mh, adam, sense, ens, copy: run only these legs once each (no "
                          "warm-up, no headline line) for hardware counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -747,6 +756,9 @@ def main():
             elif leg == "sense":
                 r = sense_leg(g, torch, 1, 0)
                 rep[leg] = {k: v["launch_us"] for k, v in r["stages"].items()}
+            elif leg == "ens":
+                r = ens_leg(g, torch, warmup=0)
+                rep[leg] = {"launch_ms": r["roofline"]["launch_ms"]}
             elif leg == "copy":
                 rep[leg] = copy_leg(torch)
             else:
