@@ -928,7 +928,8 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
             LaunchTimer tm("ens_chunk", s);
             for (int c = 0; c < nck; ++c) {
                 tm.begin();
-                GC_TRY_HIP(ens_chunk_walkers(model->kind, fp64, djob + c, demap, (int)eblk, C, s));
+                GC_TRY_HIP(ens_chunk_walkers(model->kind, fp64, djob + c, demap, (int)eblk, C,
+                                             model->Meff, s));
                 tm.end();
             }
             GC_TRY_HIP(hipStreamSynchronize(s));

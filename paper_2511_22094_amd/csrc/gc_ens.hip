@@ -46,6 +46,15 @@ struct YGlobE {
     __device__ __forceinline__ float im(int m) const { return gload(y)[(int64_t)(M + m) * n + v]; }
 };
 
+// One voxel's measurements staged in LDS: real parts, or (re, im) pairs.
+template <bool CPLX> struct YLdsE {
+    const float* p;
+    __device__ __forceinline__ float re(int m) const { return p[CPLX ? 2 * m : m]; }
+    __device__ __forceinline__ float im(int m) const { return p[2 * m + 1]; }
+};
+
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+
 __device__ __forceinline__ int first_keep_e(int t0, int burnin, int thin) {
     int t = t0 > burnin ? t0 : burnin;
     int r = (t - burnin + 1) % thin;
@@ -115,13 +124,17 @@ __global__ __launch_bounds__(kBlock) void ens_init_kernel(const MhJob* __restric
 
 // A chunk of ensemble iterations.  Block b covers voxels [b*vpb, (b+1)*vpb)
 // with vpb = kBlock / (K/2); thread (vl, i) owns walkers i and K/2 + i of voxel
-// b*vpb + vl.  The block map's lane0 is the block's first voxel.
-template <int KIND, typename R>
+// b*vpb + vl.  The block map's lane0 is the block's first voxel.  With YLDS
+// the block's measurements are staged once in LDS after the walkers (the 25
+// threads of a half-ensemble then read them there instead of through the
+// vector-memory path: one LDS read per value, no address arithmetic).
+template <int KIND, typename R, bool YLDS>
 __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restrict__ jobs,
                                                           const BlkMap* __restrict__ map) {
 #pragma clang fp contract(off)
     using Mdl = typename ModelOf<KIND, R>::T;
     constexpr int P = Mdl::P;
+    constexpr bool CPLX = Mdl::kComplex;
     extern __shared__ unsigned char smem[];
     const BlkMap bm = map[blockIdx.x];
     const MhJob& J = jobs[bm.job];
@@ -134,6 +147,18 @@ __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restri
     R* LP = X + (size_t)vpb * K * P;     // [vpb][K]
     R* TH = (R*)J.th;
     R* LLg = (R*)J.ll;
+    // [vpb][Me] measurements (Me = M, or 2 M as (re, im) pairs), after the walkers
+    const int Me = CPLX ? 2 * J.acq.M : J.acq.M;
+    float* Yl = (float*)(smem + align16((size_t)vpb * K * (P + 1) * sizeof(R)));
+    if constexpr (YLDS) {
+        // consecutive threads take consecutive voxels of one row: coalesced reads
+        for (int idx = threadIdx.x; idx < vpb * Me; idx += kBlock) {
+            const int j = idx / vpb, a = idx % vpb;
+            const int64_t va = bm.lane0 + a;
+            const int row = CPLX ? ((j & 1) ? J.acq.M + (j >> 1) : (j >> 1)) : j;
+            Yl[a * Me + j] = va < n ? gload(J.y)[(int64_t)row * n + va] : 0.f;
+        }
+    }
     // load the ensemble of every voxel of the block
     for (int idx = threadIdx.x; idx < vpb * K; idx += kBlock) {
         const int a = idx / K, k = idx % K;
@@ -197,7 +222,10 @@ __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restri
                 R ev[P];
 #pragma unroll
                 for (int p = 0; p < P; ++p) ev[p] = inb ? Y[p] : Xv[(size_t)k * P + p];
-                llp = nscale * Mdl::template sse<0>(ev, y, J.acq);
+                if constexpr (YLDS)
+                    llp = nscale * Mdl::template sse<0>(ev, YLdsE<CPLX>{Yl + vl * Me}, J.acq);
+                else
+                    llp = nscale * Mdl::template sse<0>(ev, y, J.acq);
                 const R lhs = Math<R>::ln(uniform01<R>(o.z));
                 accept = inb && (lhs < (R)(P - 1) * Math<R>::ln(z) + llp - LPv[k]);
             }
@@ -272,24 +300,33 @@ hipError_t ens_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, i
     return hipErrorInvalidValue;
 }
 
-// Launch for a job whose walker count is `walkers` (the map covers voxels in
-// groups of kBlock / (walkers / 2)); dynamic LDS = vpb * K * (P + 1) reals.
+// Launch for jobs whose walker count is `walkers` (the map covers voxels in
+// groups of kBlock / (walkers / 2)) and whose effective measurement counts are
+// at most `meff`; dynamic LDS = vpb * K * (P + 1) reals for the walkers, plus
+// vpb * meff floats of staged data when that fits in kEnsLdsData bytes.
+constexpr size_t kEnsLdsData = 64 * 1024;
 template <int KIND, typename R>
 static hipError_t ens_chunk_t(const MhJob* jobs, const BlkMap* map, int nblk, int walkers,
-                              hipStream_t s) {
+                              int meff, hipStream_t s) {
     using Mdl = typename ModelOf<KIND, R>::T;
     const int hp = walkers / 2, vpb = kBlock / hp;
     const size_t lds = (size_t)vpb * walkers * (Mdl::P + 1) * sizeof(R);
-    hipLaunchKernelGGL((ens_chunk_kernel<KIND, R>), dim3(nblk), dim3(kBlock), lds, s, jobs, map);
+    const size_t lds_y = align16(lds) + (size_t)vpb * meff * sizeof(float);
+    if (meff > 0 && lds_y <= kEnsLdsData)
+        hipLaunchKernelGGL((ens_chunk_kernel<KIND, R, true>), dim3(nblk), dim3(kBlock), lds_y, s,
+                           jobs, map);
+    else
+        hipLaunchKernelGGL((ens_chunk_kernel<KIND, R, false>), dim3(nblk), dim3(kBlock), lds, s,
+                           jobs, map);
     return hipGetLastError();
 }
 
 hipError_t ens_chunk_walkers(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, int nblk,
-                             int walkers, hipStream_t s) {
+                             int walkers, int meff, hipStream_t s) {
 #define GC_EC(K)                                                                          \
     case K:                                                                               \
-        return fp64 ? ens_chunk_t<K, double>(jobs, map, nblk, walkers, s)                 \
-                    : ens_chunk_t<K, float>(jobs, map, nblk, walkers, s);
+        return fp64 ? ens_chunk_t<K, double>(jobs, map, nblk, walkers, meff, s)           \
+                    : ens_chunk_t<K, float>(jobs, map, nblk, walkers, meff, s);
     switch (kind) {
         GC_EC(MONOEXP_T2S)
         GC_EC(MONOEXP_R2S)

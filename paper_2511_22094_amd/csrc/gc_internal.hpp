@@ -101,9 +101,10 @@ hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkM
                     int nblk, hipStream_t s);
 hipError_t mh_finalize(bool fp64, const MhJob* jobs, const BlkMap* vmap, int nblk,
                        double* out_mean, double* out_std, hipStream_t s);
-// ensemble: map rows cover groups of kBlock / (walkers / 2) voxels (lane0 = first voxel)
+// ensemble: map rows cover groups of kBlock / (walkers / 2) voxels (lane0 = first voxel);
+// meff = the largest effective measurement count (M, or 2 M if complex) of the jobs
 hipError_t ens_chunk_walkers(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, int nblk,
-                             int walkers, hipStream_t s);
+                             int walkers, int meff, hipStream_t s);
 hipError_t ens_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, int nblk,
                     hipStream_t s);
 int mh_pick_maxm(int kind, int M);

@@ -309,6 +309,7 @@ struct Group {
     std::vector<BlkMap> map;
     std::vector<Job*> owners;   // fit_step: owner per descriptor (loss / stop launches)
     std::vector<int> iter;      // fit_step: iteration of each descriptor (1-based)
+    int meff = 0;               // ens_chunk: largest effective measurement count of the jobs
 };
 
 // Enqueue one round of shared launches on the compute stream.
@@ -338,6 +339,7 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
             J->t_next = q.t1;
             if (J->ens) {
                 Group& g = find(2, J->kind, 0, J->fp64, J->C);
+                g.meff = std::max(g.meff, J->spec.model->Meff);
                 const int vpb = kBlock / (J->C / 2);
                 const int jb = (int)g.mh.size();
                 g.mh.push_back(q);
@@ -444,7 +446,7 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
         tm.begin();
         if (g.kernel == 0) GC_TRY_HIP(mh_chunk(g.kind, g.fp64, g.maxm, (const MhJob*)(dev + u.od), mp, nb, S->compute));
         else if (g.kernel == 1) GC_TRY_HIP(fit_fused(g.kind, g.maxm, (const FitJob*)(dev + u.od), mp, nb, S->compute));
-        else GC_TRY_HIP(ens_chunk_walkers(g.kind, g.fp64, (const MhJob*)(dev + u.od), mp, nb, g.walkers, S->compute));
+        else GC_TRY_HIP(ens_chunk_walkers(g.kind, g.fp64, (const MhJob*)(dev + u.od), mp, nb, g.walkers, g.meff, S->compute));
         tm.end();
     }
     for (auto& gs : steps) {
