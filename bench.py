@@ -61,20 +61,20 @@ PEAK_HBM_GBS = 8000.0
 # taken on: when their sha256 differs, `traffic` is reported as null.
 MEASURED_TRAFFIC = {
     "mh_chunk": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "d519cb75935397334892f893c4f3b818e75586425471d773b5ce36ebef63ac9e",
-        "read_bytes": 1595951932, "write_bytes": 788529152,
+        "sha256": "8b94ee27dcb491febb348dc2a8de08b7575dfb2e295353fab45a5ecdce504581",
+        "read_bytes": 1595950918, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
     "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "c0f05566bd9ebcfd4f75de3c016e78c0fa3d955308b831767f2fa67dbd59df39",
-        "read_bytes": 127183942, "write_bytes": 15728648,
+        "sha256": "2c24ff443dc84a271e697c36c0fd8fb6e3c62e99e8d05deb991fd8c3430459fc",
+        "read_bytes": 127175456, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "8b6e1a2433ae7f670e2e138d1bfa59c76ecf0176ab470ea904902336ea03f0c6",
-        "read_bytes": 112252498, "write_bytes": 100663321,
+        "sha256": "99c4d4176739ba2878b20e24d1797131b11b88ad88c59e8ee45b92a56fe1fc76",
+        "read_bytes": 112251843, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "8b6e1a2433ae7f670e2e138d1bfa59c76ecf0176ab470ea904902336ea03f0c6",
-        "read_bytes": 148140395, "write_bytes": 111472118,
+        "sha256": "99c4d4176739ba2878b20e24d1797131b11b88ad88c59e8ee45b92a56fe1fc76",
+        "read_bytes": 147831536, "write_bytes": 111472117,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
