@@ -271,6 +271,27 @@ def test_ensemble_matches_oracle(orc, prec):
         assert np.abs(zm).max() < 8 and abs(zm.mean()) < 0.5
 
 
+@pytest.mark.parametrize("model,walkers", [("gre3", 16), ("dwi2", 4), ("dwi2", 16)],
+                         ids=["gre3-16-lds-pairs", "dwi2-4-memory", "dwi2-16-lds"])
+def test_ensemble_fp64_bit_exact_other_models(orc, model, walkers):
+    """The ensemble kernel's two data paths: measurements staged in LDS (as
+    (re, im) pairs for the complex model) and, when they would not fit beside
+    the walkers (few walkers, hence many voxels per block, and 96
+    measurements), read from memory per use."""
+    d = _small(model, (2, 4, 5), 12, 0.02 if model == "dwi2" else 0.01)
+    y, yg = _data(orc, d)
+    kw = dict(n_iter=200, burnin=50, thin=5)
+    ref = orc.ensemble(d.model, d.acq, y, d.lb, d.ub, d.sigma, 6, walkers, stretch=2.0,
+                       keep_samples=True, **kw)
+    out = G().gc_mcmc(_model(d), yg, d.mask, d.lb, d.ub, 1, sigma=d.sigma, seed=6,
+                      sampler="ensemble", n_walkers=walkers, stretch=2.0, precision="fp64",
+                      samples=True, final_state=True, chunk_iters=70, **kw)
+    acc = synth.gather(out["accept"], d.mask)
+    assert np.array_equal(acc, ref["accept"])
+    np.testing.assert_allclose(out["final_state"], ref["final"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(synth.gather(out["mean"], d.mask), ref["mean"], rtol=1e-11)
+
+
 def test_mcmc_rejects_bad_arguments():
     g = G()
     m = g.Model("monoexp_t2s", te=synth.echo_times(2.0, 4.0, 12))
