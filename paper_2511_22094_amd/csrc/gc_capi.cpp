@@ -940,7 +940,7 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
             LaunchTimer tm("mh_chunk", s);
             for (int c = 0; c < nck; ++c) {
                 tm.begin();
-                GC_TRY_HIP(mh_chunk(model->kind, fp64, maxm, djob + c, dmap, (int)nblk, s));
+                GC_TRY_HIP(mh_chunk(model->kind, fp64, maxm, djob + c, dmap, (int)nblk, C, model->Meff, s));
                 tm.end();
             }
             if (timing_on()) {

@@ -97,8 +97,13 @@ struct FitJob {
 // MCMC (gc_mh.hip)
 hipError_t mh_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, int nblk,
                    hipStream_t s);
+// chains > 0: every job of the launch has that many chains, and instantiations
+// that read their data from memory then share it through LDS among the chains
+// of a voxel (when kBlock / chains * meff floats fit in kMhSharedData bytes);
+// meff = the jobs' effective measurement count (M, or 2 M if complex)
+constexpr size_t kMhSharedData = 48 * 1024;
 hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkMap* map,
-                    int nblk, hipStream_t s);
+                    int nblk, int chains, int meff, hipStream_t s);
 hipError_t mh_finalize(bool fp64, const MhJob* jobs, const BlkMap* vmap, int nblk,
                        double* out_mean, double* out_std, hipStream_t s);
 // ensemble: map rows cover groups of kBlock / (walkers / 2) voxels (lane0 = first voxel);

@@ -18,6 +18,15 @@ template <int MAXM, bool CPLX> struct YReg {
     __device__ __forceinline__ float im(int m) const { return i[CPLX ? m : 0]; }
 };
 
+// measured data staged in LDS for the chains of one voxel (any measurement
+// count): real parts, then imaginary parts
+struct YShared {
+    const float* p;
+    int M;
+    __device__ __forceinline__ float re(int m) const { return p[m]; }
+    __device__ __forceinline__ float im(int m) const { return p[M + m]; }
+};
+
 // measured data read from HBM (any measurement count)
 struct YGlob {
     const float* y;
@@ -113,8 +122,16 @@ __global__ __launch_bounds__(kBlock) void mh_init_kernel(const MhJob* __restrict
 
 // --------------------------------------------------------------------------
 // A chunk of MH iterations [t0, t1) for every (voxel, chain) lane.
+//
+// SHARED (data read from memory, chain count C dividing the block size): the
+// block with lanes [lane0, lane0 + kBlock) takes instead the C chains of the
+// kBlock / C consecutive voxels from lane0 / C on, chain fastest, and stages
+// those voxels' data once in LDS, where the C chains of a voxel read them.
+// Every (voxel, chain) pair is still run by exactly one lane of the launch,
+// with the same state and random stream, so results do not depend on SHARED.
 // --------------------------------------------------------------------------
-template <int KIND, typename R, int MAXM, int EXACT = 0, int RECUR = kRecurRuntime>
+template <int KIND, typename R, int MAXM, int EXACT = 0, int RECUR = kRecurRuntime,
+          bool SHARED = false>
 __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restrict__ jobs,
                                                          const BlkMap* __restrict__ map) {
     using Mdl = typename ModelOf<KIND, R>::T;
@@ -123,10 +140,29 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
     const BlkMap bm = map[blockIdx.x];
     const MhJob& J = jobs[bm.job];
     const int64_t n = J.n, NL = n * J.C;
-    const int64_t L = bm.lane0 + threadIdx.x;
-    if (L >= NL) return;
-    const int64_t v = L % n;
-    const int c = (int)(L / n);
+    int64_t L, v;
+    int c;
+    YShared ys{nullptr, J.acq.M};
+    if constexpr (SHARED) {
+        extern __shared__ float ysm[];   // [kBlock / C][Meff]
+        const int C = J.C, vb = kBlock / C, Me = CPLX ? 2 * J.acq.M : J.acq.M;
+        const int64_t v0 = bm.lane0 / C;
+        for (int idx = threadIdx.x; idx < vb * Me; idx += kBlock) {
+            const int j = idx / vb, a = idx % vb;   // row j, voxel v0 + a: coalesced
+            ysm[a * Me + j] = v0 + a < n ? gload(J.y)[(int64_t)j * n + v0 + a] : 0.f;
+        }
+        __syncthreads();
+        v = v0 + threadIdx.x / C;
+        c = (int)(threadIdx.x % C);
+        if (v >= n) return;
+        L = (int64_t)c * n + v;
+        ys.p = ysm + (threadIdx.x / C) * Me;
+    } else {
+        L = bm.lane0 + threadIdx.x;
+        if (L >= NL) return;
+        v = L % n;
+        c = (int)(L / n);
+    }
     const AcqDev acq = J.acq;
 
     // chain state
@@ -188,6 +224,7 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
         for (int p = 0; p < P; ++p) the[p] = inb ? thp[p] : th[p];
         R sse;
         if constexpr (MAXM > 0) sse = Mdl::template sse<MAXM, EXACT, RECUR>(the, yr, acq);
+        else if constexpr (SHARED) sse = Mdl::template sse<0>(the, ys, acq);
         else sse = Mdl::template sse<0>(the, yg, acq);
         const R llp = nscale * sse;
         const bool a = inb && (Math<R>::ln(u) < llp - ll);
@@ -298,10 +335,21 @@ static hipError_t chunk_t(const MhJob* jobs, const BlkMap* map, int nblk, hipStr
     return hipGetLastError();
 }
 
+// Data read from memory: shared through LDS by the chains of a voxel when
+// lds > 0 (see mh_chunk_kernel), else read per use by every lane.
+template <int KIND, typename R>
+static hipError_t chunk_mem_t(const MhJob* jobs, const BlkMap* map, int nblk, size_t lds,
+                              hipStream_t s) {
+    if (lds == 0) return chunk_t<KIND, R, 0>(jobs, map, nblk, s);
+    hipLaunchKernelGGL((mh_chunk_kernel<KIND, R, 0, 0, kRecurRuntime, true>), dim3(nblk),
+                       dim3(kBlock), lds, s, jobs, map);
+    return hipGetLastError();
+}
+
 // variant code = MAXM | exact << 16 | recurrence << 17 (see mh_pick_variant)
 template <int KIND, int A, int B, int C>
 static hipError_t chunk_f32(int variant, const MhJob* jobs, const BlkMap* map, int nblk,
-                            hipStream_t s) {
+                            size_t lds, hipStream_t s) {
     constexpr bool kRec = KIND == MONOEXP_T2S || KIND == MONOEXP_R2S || KIND == GRE3;
     constexpr int kExactRecur = kRec ? kRecurOn : kRecurOff;
     const int maxm = variant & 0xFFFF;
@@ -314,7 +362,7 @@ static hipError_t chunk_f32(int variant, const MhJob* jobs, const BlkMap* map, i
     if (maxm == A) return chunk_t<KIND, float, A>(jobs, map, nblk, s);
     if (maxm == B) return chunk_t<KIND, float, B>(jobs, map, nblk, s);
     if (maxm == C) return chunk_t<KIND, float, C>(jobs, map, nblk, s);
-    return chunk_t<KIND, float, 0>(jobs, map, nblk, s);
+    return chunk_mem_t<KIND, float>(jobs, map, nblk, lds, s);
 }
 
 // The exact, straight-line instantiation is used when the acquisition has
@@ -333,23 +381,26 @@ int mh_pick_variant(int kind, int M, int uniform) {
 }
 
 hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkMap* map,
-                    int nblk, hipStream_t s) {
+                    int nblk, int chains, int meff, hipStream_t s) {
+    const bool share = chains > 0 && kBlock % chains == 0 && meff > 0 &&
+                       (size_t)(kBlock / chains) * meff * sizeof(float) <= kMhSharedData;
+    const size_t lds = share ? (size_t)(kBlock / chains) * meff * sizeof(float) : 0;
     if (fp64) {
         switch (kind) {
-            case MONOEXP_T2S: return chunk_t<MONOEXP_T2S, double, 0>(jobs, map, nblk, s);
-            case MONOEXP_R2S: return chunk_t<MONOEXP_R2S, double, 0>(jobs, map, nblk, s);
-            case GRE3: return chunk_t<GRE3, double, 0>(jobs, map, nblk, s);
-            case DWI2: return chunk_t<DWI2, double, 0>(jobs, map, nblk, s);
-            case LINEAR3: return chunk_t<LINEAR3, double, 0>(jobs, map, nblk, s);
+            case MONOEXP_T2S: return chunk_mem_t<MONOEXP_T2S, double>(jobs, map, nblk, lds, s);
+            case MONOEXP_R2S: return chunk_mem_t<MONOEXP_R2S, double>(jobs, map, nblk, lds, s);
+            case GRE3: return chunk_mem_t<GRE3, double>(jobs, map, nblk, lds, s);
+            case DWI2: return chunk_mem_t<DWI2, double>(jobs, map, nblk, lds, s);
+            case LINEAR3: return chunk_mem_t<LINEAR3, double>(jobs, map, nblk, lds, s);
         }
         return hipErrorInvalidValue;
     }
     switch (kind) {
-        case MONOEXP_T2S: return chunk_f32<MONOEXP_T2S, 12, 16, 32>(maxm, jobs, map, nblk, s);
-        case MONOEXP_R2S: return chunk_f32<MONOEXP_R2S, 12, 16, 32>(maxm, jobs, map, nblk, s);
-        case GRE3: return chunk_f32<GRE3, 12, 24, 32>(maxm, jobs, map, nblk, s);
-        case DWI2: return chunk_t<DWI2, float, 0>(jobs, map, nblk, s);   // see mh_pick_variant
-        case LINEAR3: return chunk_f32<LINEAR3, 12, 16, 16>(maxm, jobs, map, nblk, s);
+        case MONOEXP_T2S: return chunk_f32<MONOEXP_T2S, 12, 16, 32>(maxm, jobs, map, nblk, lds, s);
+        case MONOEXP_R2S: return chunk_f32<MONOEXP_R2S, 12, 16, 32>(maxm, jobs, map, nblk, lds, s);
+        case GRE3: return chunk_f32<GRE3, 12, 24, 32>(maxm, jobs, map, nblk, lds, s);
+        case DWI2: return chunk_mem_t<DWI2, float>(jobs, map, nblk, lds, s);   // see mh_pick_variant
+        case LINEAR3: return chunk_f32<LINEAR3, 12, 16, 16>(maxm, jobs, map, nblk, lds, s);
     }
     return hipErrorInvalidValue;
 }
