@@ -61,20 +61,20 @@ PEAK_HBM_GBS = 8000.0
 # taken on: when their sha256 differs, `traffic` is reported as null.
 MEASURED_TRAFFIC = {
     "mh_chunk": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "8b94ee27dcb491febb348dc2a8de08b7575dfb2e295353fab45a5ecdce504581",
-        "read_bytes": 1595950918, "write_bytes": 788529152,
+        "sha256": "fe6f1fb42a67f76b64a416d0457d3f1204c1d150362d1f4428856f8c579ab550",
+        "read_bytes": 1595949552, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
     "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "2c24ff443dc84a271e697c36c0fd8fb6e3c62e99e8d05deb991fd8c3430459fc",
-        "read_bytes": 127175456, "write_bytes": 15728648,
+        "sha256": "d7f72d664c4d10908f529d2df20c4d4e1349c3d92551a34789ccffbf819b6759",
+        "read_bytes": 127206688, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "99c4d4176739ba2878b20e24d1797131b11b88ad88c59e8ee45b92a56fe1fc76",
-        "read_bytes": 112251843, "write_bytes": 100663321,
+        "sha256": "507f17098a9bed05bcd421ada5ce1b058d15134190b3f264f043e7f27f45a22c",
+        "read_bytes": 112252178, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "99c4d4176739ba2878b20e24d1797131b11b88ad88c59e8ee45b92a56fe1fc76",
-        "read_bytes": 147831536, "write_bytes": 111472117,
+        "sha256": "507f17098a9bed05bcd421ada5ce1b058d15134190b3f264f043e7f27f45a22c",
+        "read_bytes": 147782953, "write_bytes": 111472117,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
