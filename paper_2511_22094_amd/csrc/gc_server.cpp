@@ -302,14 +302,14 @@ static int prepare_job(gc_server* S, Job* J) {
 // One group of same-kernel work in a round: descriptors + block work-list.
 struct Group {
     int kernel;   // 0 mh_chunk, 1 fit_fused, 2 ens_chunk, 3 fit_step
-    int kind, maxm, walkers;
+    int kind, maxm, walkers;   // walkers: ensemble walkers, or the shared chain count (mh_chunk)
     bool fp64;
     std::vector<MhJob> mh;
     std::vector<FitJob> fit;
     std::vector<BlkMap> map;
     std::vector<Job*> owners;   // fit_step: owner per descriptor (loss / stop launches)
     std::vector<int> iter;      // fit_step: iteration of each descriptor (1-based)
-    int meff = 0;               // ens_chunk: largest effective measurement count of the jobs
+    int meff = 0;               // mh_chunk / ens_chunk: largest effective measurement count
 };
 
 // Enqueue one round of shared launches on the compute stream.
@@ -345,7 +345,13 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
                 g.mh.push_back(q);
                 for (int64_t v0 = 0; v0 < J->n; v0 += vpb) g.map.push_back(BlkMap{jb, 0, v0});
             } else {
-                Group& g = find(0, J->kind, J->fp64 ? 0 : J->maxm, J->fp64, 0);
+                // instantiations that read their data from memory share it among
+                // the chains of a voxel when all jobs of the launch have the same
+                // chain count dividing the block: such jobs are grouped by it
+                const bool mem = J->fp64 || (J->maxm & 0xFFFF) == 0;
+                const int share = mem && kBlock % J->C == 0 ? J->C : 0;
+                Group& g = find(0, J->kind, J->fp64 ? 0 : J->maxm, J->fp64, share);
+                g.meff = std::max(g.meff, J->spec.model->Meff);
                 const int jb = (int)g.mh.size();
                 g.mh.push_back(q);
                 const int64_t NL = J->n * J->C;
@@ -444,7 +450,7 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
         LaunchTimer tm(g.kernel == 0 ? "mh_chunk" : (g.kernel == 1 ? "fit_fused" : "ens_chunk"),
                        S->compute);
         tm.begin();
-        if (g.kernel == 0) GC_TRY_HIP(mh_chunk(g.kind, g.fp64, g.maxm, (const MhJob*)(dev + u.od), mp, nb, 0, 0, S->compute));
+        if (g.kernel == 0) GC_TRY_HIP(mh_chunk(g.kind, g.fp64, g.maxm, (const MhJob*)(dev + u.od), mp, nb, g.walkers, g.meff, S->compute));
         else if (g.kernel == 1) GC_TRY_HIP(fit_fused(g.kind, g.maxm, (const FitJob*)(dev + u.od), mp, nb, S->compute));
         else GC_TRY_HIP(ens_chunk_walkers(g.kind, g.fp64, (const MhJob*)(dev + u.od), mp, nb, g.walkers, g.meff, S->compute));
         tm.end();
