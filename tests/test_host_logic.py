@@ -39,3 +39,16 @@ def test_sense_draw_is_seeded_and_shaped():
     assert a.noise.shape == (2, 4, 16, 32) and a.mask.shape == (2, 16, 32)
     assert np.array_equal(a.truth, b.truth) and np.array_equal(a.noise, b.noise)
     assert np.abs(a.coils).max() <= 1.0 + 1e-12
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU; asking for more exits with a message and
+    status 2 before touching a device."""
+    import subprocess
+    import sys
+    from pathlib import Path
+    root = Path(__file__).resolve().parents[1]
+    r = subprocess.run([sys.executable, str(root / "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
