@@ -345,7 +345,12 @@ int gc_sense_adjoint(const gc_sense_problem *prob, const float *kspace, float *o
                      const gc_exec *exec);
 
 /* ------------------------------------------------------------------------
- * Counter-based random stream (for bit-exact tests against the oracle).
+ * Counter-based random stream.  The paper states that its MCMC solver gives
+ * the same numbers on CPU and GPU (§2.2.2, last paragraph; Abstract); here
+ * every random draw of the samplers is a pure function of (seed; voxel,
+ * chain | purpose, iteration, block) through Philox4x32-10 (Salmon et al.,
+ * SC'11), so a CPU implementation reproduces the GPU's draws exactly.  These
+ * entry points expose the stream for that check.
  * ------------------------------------------------------------------------ */
 /* out[n][4] = Philox4x32-10(ctr[n][4], key = (seed lo, seed hi)) */
 int gc_philox(uint64_t seed, const uint32_t *ctr, int64_t n, uint32_t *out,
@@ -373,7 +378,11 @@ int gc_timing_get(const char *family, double *total_ms, int64_t *launches);
 int gc_timing_reset(void);
 
 /* ------------------------------------------------------------------------
- * Continuous-batching server.  Jobs arrive with host buffers; a scheduler
+ * Continuous-batching server.  The paper's back end batches work to fit GPU
+ * memory (Abstract) and names memory-efficient batching of large or many
+ * datasets as future work (§4, Discussion); this server admits fit and MCMC
+ * jobs by device-memory footprint and runs them in shared launches.
+ * Jobs arrive with host buffers; a scheduler
  * thread admits them while their device footprint fits the HBM budget and
  * a slot is free, packs them, and advances all resident jobs together in
  * chunks of iterations (shared launches per model); finished jobs are
@@ -398,7 +407,8 @@ enum { GC_JOB_QUEUED = 0, GC_JOB_RUNNING = 1, GC_JOB_DONE = 2, GC_JOB_FAILED = 3
 
 typedef struct {
     int kind;                  /* GC_JOB_FIT or GC_JOB_MCMC */
-    const gc_model *model;     /* must outlive the job */
+    const gc_model *model;     /* the server keeps a reference until the job
+                                  finishes: gc_model_destroy may come earlier */
     gc_volume data;            /* host memory */
     const uint8_t *mask;       /* host, or NULL = all voxels */
     gc_bounds bounds;          /* x0_map, if any, host memory */
@@ -428,6 +438,11 @@ int gc_poll(gc_server *srv, uint64_t job_id, int *state);
  * result code.  GC_E_TIMEOUT if it is still running. */
 int gc_wait(gc_server *srv, uint64_t job_id, int timeout_ms, int *job_status);
 int gc_cancel(gc_server *srv, uint64_t job_id);
+/* Forgets a finished (done, failed or cancelled) job: its record is freed
+ * and its id becomes unknown (GC_E_NOTFOUND afterwards).  GC_E_INVAL while
+ * the job is queued or running.  A long-running server keeps every job's
+ * record until it is released or the server is destroyed. */
+int gc_release(gc_server *srv, uint64_t job_id);
 /* Per-job latency (submit -> result) in seconds, for finished jobs. */
 int gc_job_latency(gc_server *srv, uint64_t job_id, double *seconds);
 int gc_server_stats(gc_server *srv, gc_stats *stats);

@@ -163,6 +163,7 @@ _sig = {
     "gc_poll": ([P, c_uint64, ctypes.POINTER(c_int)], c_int),
     "gc_wait": ([P, c_uint64, c_int, ctypes.POINTER(c_int)], c_int),
     "gc_cancel": ([P, c_uint64], c_int),
+    "gc_release": ([P, c_uint64], c_int),
     "gc_job_latency": ([P, c_uint64, ctypes.POINTER(c_double)], c_int),
     "gc_server_stats": ([P, ctypes.POINTER(gc_stats)], c_int),
     "gc_server_destroy": ([P], c_int),
@@ -677,7 +678,8 @@ def gc_philox_uniform_normal(seed: int, ctr, precision="fp32"):
 # ------------------------------------------------------------------ server
 class Server:
     """Continuous-batching server (gc_server_*).  Jobs carry host (numpy)
-    arrays; the server keeps them alive until the job is waited for."""
+    arrays; the server keeps them (and the job's Model) alive until the job is
+    waited for, then releases the job's record on both sides."""
 
     def __init__(self, device=0, hbm_budget=0, max_slots=0, chunk_iters=0, baseline=False):
         cfg = gc_server_cfg(device, hbm_budget, max_slots, chunk_iters, 1 if baseline else 0)
@@ -685,9 +687,10 @@ class Server:
         _check(_L.gc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
         self._jobs = {}
+        self._done = {}    # released job id -> (state, latency in s or None)
 
     def _common(self, model, y, mask, lb, ub, x0, x0_map):
-        keep = []
+        keep = [model]
         y = np.ascontiguousarray(y, dtype=np.float32)
         nx, ny, nz = _shape3(y, model)
         keep.append(y)
@@ -777,17 +780,32 @@ class Server:
         return jid.value
 
     def poll(self, jid) -> str:
+        if jid in self._done:
+            return self._done[jid][0]
         st = c_int()
         _check(_L.gc_poll(self.handle, jid, ctypes.byref(st)))
         return JOB_STATES[st.value]
 
     def wait(self, jid, timeout_ms=-1):
-        """Waits for a job; returns its result dict (raises GcError if it failed)."""
+        """Waits for a job; returns its result dict (raises GcError if it
+        failed).  The job is then released: its buffers are no longer held
+        and poll() / latency() answer from what was recorded here."""
         st = c_int()
         _check(_L.gc_wait(self.handle, jid, timeout_ms, ctypes.byref(st)))
         _, _, out = self._jobs[jid]
-        if st.value != GC_OK:
-            raise GcError(st.value, last_error())
+        err = None if st.value == GC_OK else GcError(st.value, last_error())
+        state = c_int()
+        _check(_L.gc_poll(self.handle, jid, ctypes.byref(state)))
+        lat = None
+        if st.value == GC_OK:
+            s = c_double()
+            _check(_L.gc_job_latency(self.handle, jid, ctypes.byref(s)))
+            lat = s.value
+        _check(_L.gc_release(self.handle, jid))
+        self._done[jid] = (JOB_STATES[state.value], lat)
+        del self._jobs[jid]
+        if err is not None:
+            raise err
         r = dict(out)
         if "report" in r:
             rep = r.pop("report")
@@ -799,6 +817,10 @@ class Server:
         _check(_L.gc_cancel(self.handle, jid))
 
     def latency(self, jid) -> float:
+        if jid in self._done:
+            if self._done[jid][1] is None:
+                raise GcError(-1, "job not finished successfully")
+            return self._done[jid][1]
         s = c_double()
         _check(_L.gc_job_latency(self.handle, jid, ctypes.byref(s)))
         return s.value

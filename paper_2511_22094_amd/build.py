@@ -8,6 +8,7 @@ know that feature; the warning is expected.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -16,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libgacelle.so")
-SOURCES = ["gc_pack.hip", "gc_mh.hip", "gc_ens.hip", "gc_fit.hip", "gc_sense.hip", "gc_capi.cpp",
+SOURCES = ["gc_pack.hip", "gc_mh.hip", "gc_ens.hip", "gc_fit.hip", "gc_sense.hip", "gc_capi.cpp", "gc_variants.cpp",
            "gc_timing.cpp", "gc_server.cpp"]
 ARCH = os.environ.get("GACELLE_ARCH", "gfx950")
 
@@ -25,9 +26,33 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 
-def _compile(src: str) -> str:
+def source_files():
+    """Every file the library is compiled from (sorted, repository-relative)."""
+    root = os.path.dirname(HERE)
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".hpp", ".h")))
+    files = [os.path.join("paper_2511_22094_amd", "csrc", f) for f in names]
+    files.append(os.path.join("include", "gacelle.h"))
+    files.append(os.path.join("paper_2511_22094_amd", "build.py"))
+    return root, files
+
+
+def source_hash() -> str:
+    """sha256 (first 16 hex digits) over the library's sources and this build
+    script; embedded in the library and returned by gc_version(), so a run can
+    tell whether the library it loaded was built from the sources beside it."""
+    root, files = source_files()
+    h = hashlib.sha256()
+    for f in files:
+        h.update(f.encode() + b"\0")
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+        h.update(b"\0")
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, extra=()) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *COMMON, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in r.stderr.splitlines() if noise not in l)
@@ -40,8 +65,9 @@ def _compile(src: str) -> str:
 
 def build(jobs: int = 6) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    tag = [f'-DGC_SOURCE_HASH="{source_hash()}"']
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda f: _compile(f, tag if f == "gc_capi.cpp" else ()), SOURCES))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
            "-lpthread"]

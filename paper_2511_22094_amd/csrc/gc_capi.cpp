@@ -78,6 +78,16 @@ hipError_t Scratch::alloc(void** p, size_t bytes) {
     return e;
 }
 
+// The host-only test build of the scheduler (a stand-in runtime on the CPU)
+// observes the arena's chunks and blocks to check every access of the
+// stand-in kernels against the blocks live at that moment.
+#ifdef GC_HOST_HARNESS
+extern "C" void gc_harness_arena_event(int op, void* p, size_t bytes);
+#define GC_ARENA_EVENT(op, p, b) gc_harness_arena_event(op, p, b)
+#else
+#define GC_ARENA_EVENT(op, p, b) ((void)0)
+#endif
+
 hipError_t DevArena::alloc(void** p, size_t bytes) {
     std::lock_guard<std::mutex> lk(mu);
     bytes = (bytes + 255) / 256 * 256;
@@ -87,6 +97,7 @@ hipError_t DevArena::alloc(void** p, size_t bytes) {
             c.size = std::max(bytes, chunk_bytes);
             hipError_t e = hipMalloc((void**)&c.base, c.size);
             if (e != hipSuccess) return e;
+            GC_ARENA_EVENT(0, c.base, c.size);
             c.free_[0] = c.size;
             chunks.push_back(std::move(c));
         }
@@ -99,6 +110,7 @@ hipError_t DevArena::alloc(void** p, size_t bytes) {
             *p = c.base + off;
             used[c.base + off] = {ci, bytes};
             in_use += bytes;
+            GC_ARENA_EVENT(1, *p, bytes);
             return hipSuccess;
         }
     }
@@ -111,6 +123,7 @@ void DevArena::free(void* p) {
     if (it == used.end()) return;
     Chunk& c = chunks[it->second.first];
     size_t off = (size_t)((char*)p - c.base), len = it->second.second;
+    GC_ARENA_EVENT(2, p, len);
     used.erase(it);
     in_use -= len;
     // coalesce with the free neighbours inside the chunk
@@ -129,8 +142,32 @@ void DevArena::free(void* p) {
     c.free_[off] = len;
 }
 
+bool DevArena::owns(const void* p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = used.upper_bound((char*)p);
+    if (it == used.begin()) return false;
+    --it;
+    return (const char*)p + bytes <= it->first + it->second.second;
+}
+
 DevArena::~DevArena() {
     for (auto& c : chunks) (void)hipFree(c.base);
+}
+
+void model_retain(const gc_model* m) {
+    if (m) m->refs.fetch_add(1);
+}
+
+void model_release(const gc_model* m) {
+    if (!m || m->refs.fetch_sub(1) != 1) return;
+    for (auto& kv : m->dev) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(kv.first);
+        (void)hipFree(kv.second.buf);
+        (void)hipSetDevice(prev);
+    }
+    delete m;
 }
 
 int stage_in(Scratch& sc, const void* p, size_t bytes, int mem_kind, const void** dptr) {
@@ -475,7 +512,10 @@ using namespace gc;
 extern "C" {
 
 const char* gc_last_error(void) { return g_err.c_str(); }
-const char* gc_version(void) { return "gacelle-mi355x 0.1 (gfx950)"; }
+#ifndef GC_SOURCE_HASH
+#define GC_SOURCE_HASH "unknown"
+#endif
+const char* gc_version(void) { return "gacelle-mi355x 0.2 (gfx950) src " GC_SOURCE_HASH; }
 
 int gc_model_create(const char* name, const gc_acq* acq, gc_model** out) {
     GC_GUARD_BEGIN
@@ -547,15 +587,7 @@ const char* gc_model_param_name(const gc_model* m, int p) {
 }
 
 int gc_model_destroy(gc_model* m) {
-    if (!m) return GC_OK;
-    for (auto& kv : m->dev) {
-        int prev = 0;
-        (void)hipGetDevice(&prev);
-        (void)hipSetDevice(kv.first);
-        (void)hipFree(kv.second.buf);
-        (void)hipSetDevice(prev);
-    }
-    delete m;
+    model_release(m);
     return GC_OK;
 }
 

@@ -325,14 +325,6 @@ __global__ __launch_bounds__(kBlock) void fit_fused_kernel(const FitJob* __restr
     }
 }
 
-int fit_pick_maxm(int kind, int M) {
-    if (kind == GRE3) return M <= 12 ? 12 : (M <= 24 ? 24 : (M <= 32 ? 32 : 0));
-    // dwi2: the shell-by-shell loop over data read per use measured 15 %
-    // faster than 96 measurements held in registers (two waves per SIMD)
-    if (kind == DWI2) return 0;
-    return M <= 12 ? 12 : (M <= 16 ? 16 : (M <= 32 ? 32 : 0));
-}
-
 template <int KIND, int MAXM>
 static hipError_t fused_t(const FitJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
     hipLaunchKernelGGL((fit_fused_kernel<KIND, MAXM>), dim3(nblk), dim3(kBlock), 0, s, jobs, map);

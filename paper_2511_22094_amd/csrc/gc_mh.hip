@@ -293,19 +293,6 @@ __global__ __launch_bounds__(kBlock) void mh_finalize_kernel(const MhJob* __rest
 }
 
 // ---------------------------------------------------------------- dispatch
-// Register-resident data sizes instantiated per model (measurement counts);
-// anything else runs the HBM-read variant (MAXM = 0).
-int mh_pick_maxm(int kind, int M) {
-    static const int mono[] = {12, 16, 32};
-    static const int gre[] = {12, 24, 32};
-    if (kind == DWI2) return 0;
-    const int* list = kind == GRE3 ? gre : mono;
-    if (kind == LINEAR3) return M <= 12 ? 12 : (M <= 16 ? 16 : 0);
-    for (int i = 0; i < 3; ++i)
-        if (M <= list[i]) return list[i];
-    return 0;
-}
-
 template <int KIND, typename R>
 static hipError_t init_t(const MhJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
     hipLaunchKernelGGL((mh_init_kernel<KIND, R>), dim3(nblk), dim3(kBlock), 0, s, jobs, map);
@@ -363,21 +350,6 @@ static hipError_t chunk_f32(int variant, const MhJob* jobs, const BlkMap* map, i
     if (maxm == B) return chunk_t<KIND, float, B>(jobs, map, nblk, s);
     if (maxm == C) return chunk_t<KIND, float, C>(jobs, map, nblk, s);
     return chunk_mem_t<KIND, float>(jobs, map, nblk, lds, s);
-}
-
-// The exact, straight-line instantiation is used when the acquisition has
-// exactly MAXM measurements and -- for the exponential-decay models -- equally
-// spaced echoes (the recurrence then applies unconditionally).
-int mh_pick_variant(int kind, int M, int uniform) {
-    // dwi2 reads its data from memory: with up to 96 measurements per lane in
-    // registers (and the straight-line form's hoisted acquisition values) the
-    // kernel runs at one or two waves per SIMD, which measured 1.2x (register
-    // loop) to 5.8x (straight line) slower than the memory-read loop
-    if (kind == DWI2) return 0;
-    const int maxm = mh_pick_maxm(kind, M);
-    const bool rec_model = kind == MONOEXP_T2S || kind == MONOEXP_R2S || kind == GRE3;
-    const bool exact = maxm == M && (!rec_model || uniform);
-    return maxm | (exact ? 1 << 16 : 0);
 }
 
 hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkMap* map,

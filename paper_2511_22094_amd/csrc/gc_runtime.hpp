@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <map>
@@ -31,6 +32,9 @@ struct gc_model {
     };
     mutable std::mutex mu;
     mutable std::map<int, DevAcq> dev;    // per device ordinal
+    // references: the creator's (dropped by gc_model_destroy) plus one per
+    // server job that has not finished; the last one frees the model
+    mutable std::atomic<int> refs{1};
 };
 
 namespace gc {
@@ -83,6 +87,8 @@ struct DevArena {
     size_t in_use = 0;
     hipError_t alloc(void** p, size_t bytes);
     void free(void* p);
+    // true if [p, p + bytes) lies inside one block handed out and not freed
+    bool owns(const void* p, size_t bytes);
     ~DevArena();
 };
 
@@ -99,6 +105,10 @@ struct Scratch {
         return alloc((void**)p, n * sizeof(T));
     }
 };
+
+// Model references (server jobs keep their model alive until they finish).
+void model_retain(const gc_model* m);
+void model_release(const gc_model* m);
 
 // Device-side acquisition of a model on the current device.
 int model_acq(const gc_model* m, int device, AcqDev* out);

@@ -307,10 +307,111 @@ struct Group {
     std::vector<MhJob> mh;
     std::vector<FitJob> fit;
     std::vector<BlkMap> map;
-    std::vector<Job*> owners;   // fit_step: owner per descriptor (loss / stop launches)
+    std::vector<Job*> owners;   // owner job per descriptor
     std::vector<int> iter;      // fit_step: iteration of each descriptor (1-based)
     int meff = 0;               // mh_chunk / ens_chunk: largest effective measurement count
 };
+
+// Host-side check of a round before anything of it is enqueued: every row of
+// a group's work-list names one of the group's descriptors and a lane range
+// inside that job, and every array a descriptor points to lies inside a live
+// block of the server's arena, large enough for what the kernels index.  A
+// failure ends the round with an error instead of a launch that could touch
+// memory outside its job.
+static int check_arr(gc_server* S, const Job* J, const void* p, size_t bytes, const char* what) {
+    if (bytes == 0) return GC_OK;
+    if (p && S->arena.owns(p, bytes)) return GC_OK;
+    set_error("job %llu: %s (%zu bytes at %p) is not inside a live block of the server's memory",
+              (unsigned long long)J->id, what, bytes, p);
+    return GC_E_DEVICE;
+}
+
+static int check_group(gc_server* S, const Group& g) {
+    int rc;
+#define GC_CHECK_ARR(p, b, w) \
+    if ((rc = check_arr(S, J, (p), (b), (w)))) return rc
+    const size_t nd = g.kernel == 0 || g.kernel == 2 ? g.mh.size() : g.fit.size();
+    GC_REQUIRE(g.owners.size() == nd, GC_E_DEVICE, "round: %zu descriptors, %zu owners", nd,
+               g.owners.size());
+    for (size_t k = 0; k < nd; ++k) {
+        const Job* J = g.owners[k];
+        const int Meff = J->spec.model->Meff;
+        if (g.kernel == 0 || g.kernel == 2) {
+            const MhJob& q = g.mh[k];
+            const int64_t n = q.n, NL = n * (int64_t)q.C;
+            const size_t rs = g.fp64 ? 8 : 4, P = (size_t)q.P;
+            GC_REQUIRE(n == J->n && q.C == J->C && q.P == J->spec.model->P, GC_E_DEVICE,
+                       "job %llu: descriptor sizes differ from the job's", (unsigned long long)J->id);
+            GC_REQUIRE(g.walkers == 0 || q.C == g.walkers, GC_E_DEVICE,
+                       "job %llu: %d chains in a launch for %d", (unsigned long long)J->id, q.C,
+                       g.walkers);
+            GC_REQUIRE(q.samples == nullptr && q.init_state == nullptr, GC_E_DEVICE,
+                       "job %llu: server jobs keep no samples and start fresh",
+                       (unsigned long long)J->id);
+            GC_CHECK_ARR(q.th, P * NL * rs, "chain states");
+            GC_CHECK_ARR(q.ll, NL * rs, "log-likelihoods");
+            GC_CHECK_ARR(q.acc, NL * 4, "accept counts");
+            GC_CHECK_ARR(q.mean, P * NL * 8, "Welford means");
+            GC_CHECK_ARR(q.m2, P * NL * 8, "Welford M2");
+            GC_CHECK_ARR(q.y, (size_t)Meff * n * 4, "data");
+            if (q.w) GC_CHECK_ARR(q.w, n * 4, "weights");
+            if (q.x0map) GC_CHECK_ARR(q.x0map, P * n * 4, "start map");
+        } else {
+            const FitJob& q = g.fit[k];
+            const int64_t n = q.n;
+            const size_t P = (size_t)q.P, np = P * n * 4;
+            GC_REQUIRE(n == J->n && q.P == J->spec.model->P, GC_E_DEVICE,
+                       "job %llu: descriptor sizes differ from the job's", (unsigned long long)J->id);
+            GC_CHECK_ARR(q.y, (size_t)Meff * n * 4, "data");
+            if (q.w) GC_CHECK_ARR(q.w, n * 4, "weights");
+            if (q.x0map) GC_CHECK_ARR(q.x0map, np, "start map");
+            GC_CHECK_ARR(q.m, np, "first moments");
+            GC_CHECK_ARR(q.v, np, "second moments");
+            if (q.prior_mask) {
+                GC_CHECK_ARR(q.mu, np, "prior means");
+                GC_CHECK_ARR(q.sigma, np, "prior SDs");
+            }
+            if (g.kernel == 1) {
+                GC_CHECK_ARR(q.u, np, "iterate");
+                if (q.loss_v) GC_CHECK_ARR(q.loss_v, n * 4, "per-voxel losses");
+            } else {
+                GC_CHECK_ARR(q.u_in, np, "iterate (read)");
+                GC_CHECK_ARR(q.u_out, np, "iterate (written)");
+                GC_CHECK_ARR(q.stop, 8, "stop flags");
+                if (q.tv_mask && q.tv_kind != GC_TV_GRAPH) GC_CHECK_ARR(q.nbr, 6 * n * 4, "neighbours");
+                if (q.tv_mask && q.tv_kind == GC_TV_GRAPH) {
+                    GC_CHECK_ARR(q.g_rowptr, (n + 1) * 8, "graph offsets");
+                    if (J->spec.adam.graph_nnz > 0)
+                        GC_CHECK_ARR(q.g_col, (size_t)J->spec.adam.graph_nnz * 4, "graph columns");
+                }
+                if (q.record) GC_CHECK_ARR(q.partial, (size_t)J->nblk * 4, "loss partials");
+            }
+        }
+    }
+#undef GC_CHECK_ARR
+    // work-list rows
+    for (size_t r = 0; r < g.map.size(); ++r) {
+        const BlkMap& b = g.map[r];
+        GC_REQUIRE(b.job >= 0 && (size_t)b.job < nd, GC_E_DEVICE,
+                   "round: work-list row %zu names descriptor %d of %zu", r, b.job, nd);
+        const Job* J = g.owners[b.job];
+        int64_t lanes;
+        if (g.kernel == 0) lanes = g.mh[b.job].n * g.mh[b.job].C;
+        else if (g.kernel == 2) lanes = g.mh[b.job].n;          // rows cover voxel groups
+        else lanes = g.fit[b.job].n;
+        GC_REQUIRE(b.lane0 >= 0 && b.lane0 < lanes, GC_E_DEVICE,
+                   "job %llu: work-list row %zu starts at lane %lld of %lld",
+                   (unsigned long long)J->id, r, (long long)b.lane0, (long long)lanes);
+        if (g.kernel == 3) {
+            const FitJob& q = g.fit[b.job];
+            GC_REQUIRE((int64_t)r >= q.blk0 && (int64_t)r - q.blk0 < J->nblk &&
+                           b.lane0 == ((int64_t)r - q.blk0) * kBlock,
+                       GC_E_DEVICE, "job %llu: work-list row %zu outside the job's rows",
+                       (unsigned long long)J->id, r);
+        }
+    }
+    return GC_OK;
+}
 
 // Enqueue one round of shared launches on the compute stream.
 static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void*& rec_host,
@@ -343,6 +444,7 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
                 const int vpb = kBlock / (J->C / 2);
                 const int jb = (int)g.mh.size();
                 g.mh.push_back(q);
+                g.owners.push_back(J);
                 for (int64_t v0 = 0; v0 < J->n; v0 += vpb) g.map.push_back(BlkMap{jb, 0, v0});
             } else {
                 // instantiations that read their data from memory share it among
@@ -354,6 +456,7 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
                 g.meff = std::max(g.meff, J->spec.model->Meff);
                 const int jb = (int)g.mh.size();
                 g.mh.push_back(q);
+                g.owners.push_back(J);
                 const int64_t NL = J->n * J->C;
                 for (int64_t l0 = 0; l0 < NL; l0 += kBlock) g.map.push_back(BlkMap{jb, 0, l0});
             }
@@ -371,6 +474,7 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
             Group& g = find(1, J->kind, J->maxm, false, 0);
             const int jb = (int)g.fit.size();
             g.fit.push_back(q);
+            g.owners.push_back(J);
             for (int64_t v0 = 0; v0 < J->n; v0 += kBlock) g.map.push_back(BlkMap{jb, 0, v0});
         } else {
             stepjobs.push_back(J);
@@ -414,6 +518,15 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
         if (gs.empty()) break;
         steps.push_back(std::move(gs));
     }
+    for (auto& g : groups) {
+        int rc = check_group(S, g);
+        if (rc) return rc;
+    }
+    for (auto& gs : steps)
+        for (auto& g : gs) {
+            int rc = check_group(S, g);
+            if (rc) return rc;
+        }
     // upload all descriptors of the round through one pinned buffer
     size_t bytes = 0;
     auto add = [&](size_t b) { size_t o = bytes; bytes += (b + 255) / 256 * 256; return o; };
@@ -626,6 +739,8 @@ static void complete_job(gc_server* S, Job* J, int status) {
     }
     S->used -= J->footprint;
     S->resident.erase(std::remove(S->resident.begin(), S->resident.end(), J), S->resident.end());
+    model_release(J->spec.model);   // the job's reference (taken at submission)
+    J->spec.model = nullptr;
     S->cv.notify_all();
 }
 
@@ -655,6 +770,8 @@ static void scheduler(gc_server* S) {
                     J->state = GC_JOB_CANCELLED;
                     J->status = GC_E_CANCELLED;
                     S->n_cancel++;
+                    model_release(J->spec.model);
+                    J->spec.model = nullptr;
                     it = S->queue.erase(it);
                     S->cv.notify_all();
                     continue;
@@ -863,6 +980,7 @@ int gc_submit(gc_server* S, const gc_job* job, uint64_t* job_id) {
         GC_REQUIRE(!S->stopping, GC_E_INVAL, "server is shutting down");
         J->id = S->next_id++;
         J->t_submit = now_seconds();
+        model_retain(m);   // released when the job finishes
         *job_id = J->id;
         S->queue.push_back(J->id);
         S->jobs[J->id] = std::move(J);
@@ -898,6 +1016,17 @@ int gc_wait(gc_server* S, uint64_t id, int timeout_ms, int* job_status) {
     }
     if (job_status) *job_status = J->status;
     if (J->status != GC_OK && !J->err.empty()) set_error("%s", J->err.c_str());
+    return GC_OK;
+}
+
+int gc_release(gc_server* S, uint64_t id) {
+    GC_REQUIRE(S, GC_E_INVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(id);
+    GC_REQUIRE(it != S->jobs.end(), GC_E_NOTFOUND, "unknown job %llu", (unsigned long long)id);
+    GC_REQUIRE(it->second->state >= GC_JOB_DONE, GC_E_INVAL,
+               "job %llu is still queued or running", (unsigned long long)id);
+    S->jobs.erase(it);
     return GC_OK;
 }
 

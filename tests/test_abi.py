@@ -48,6 +48,8 @@ def test_host_only_entry_points(lib):
     from paper_2511_22094_amd import lib as load
     g = load()
     assert "gfx950" in g.gc_version()
+    from paper_2511_22094_amd import build
+    assert build.source_hash() in g.gc_version()
     assert g.gc_burnin_from_ratio(0.1, 25000) == 2500
     m = g.Model("gre3", te=[2.0 + 2 * i for i in range(24)])
     assert (m.n_params, m.n_meas_eff, m.is_complex) == (9, 48, True)

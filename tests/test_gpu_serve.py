@@ -2,6 +2,7 @@
 synchronous call (alone) whatever the mix, the admission budget, the
 arrival pattern or the comparison (one-job-per-launch) mode; failures and
 cancellations stay with their job."""
+import ctypes
 import time
 
 import numpy as np
@@ -166,3 +167,31 @@ def test_oversized_job_is_refused():
         with pytest.raises(g.GcError) as e:
             srv.submit_mcmc(m, y, None, d.lb, d.ub, 1, 100, 10, 1, sigma=0.01)
         assert e.value.code == -3
+
+
+def test_jobs_outlive_their_model_handle_and_are_released(specs_and_alone):
+    """A caller may destroy its model right after submitting (the server holds
+    its own reference), and waited-for jobs are released on both sides."""
+    import gc as pygc
+    g = G()
+    specs, alone = specs_and_alone
+    with g.Server(chunk_iters=64) as srv:
+        ids = []
+        for i in (1, 5):
+            k, d, y, kw = specs[i]
+            tmp = []
+            ids.append((i, _submit(srv, g, k, d, y, kw, tmp)))
+            # drop the caller's handle at once, as a C caller may
+            m = tmp.pop()
+            g._L.gc_model_destroy(m.handle)
+            m.handle = None
+            del m, tmp
+            pygc.collect()
+        for i, jid in ids:
+            r = srv.wait(jid)
+            _same(specs[i][0], r, alone[i])
+            assert srv.poll(jid) == "done" and srv.latency(jid) > 0
+            assert jid not in srv._jobs
+            st = ctypes.c_int()
+            assert g._L.gc_poll(srv.handle, jid, ctypes.byref(st)) == -8   # released
+        assert srv.stats()["completed"] == 2
