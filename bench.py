@@ -2,25 +2,26 @@
 """Throughput benchmark of the voxel-parallel fitting hot path on one MI355X.
 
 Headline (``value``): Metropolis-Hastings voxel-chain-iterations per second
-on the 3-pool complex GRE workload (128 x 128 x 64 voxels, 24 echoes,
-4 chains x 5,000 iterations, burn-in 500, thinning 100, FP32 chains with
-FP64 moments).  One step = one gc_mcmc call over the whole volume with the
-data already resident in HBM (pack -> init -> fused MH chunks -> moment
-merge -> scatter to grid maps).
+on the whole-brain-sized 3-pool complex GRE workload (240 x 240 x 180 grid,
+1,199,888-voxel ellipsoid mask, 24 echoes, SNR 50, 8 chains x 10,000
+iterations, burn-in 1,000, thinning 10, FP32 chains with FP64 moments).  One
+step = one gc_mcmc call over the whole volume with the data already resident
+in HBM (pack -> init -> fused MH chunks -> moment merge -> scatter to grid
+maps).  The 128 x 128 x 64 volume (4 chains x 5,000) is a second MH leg.
 
-Second leg (``adam``): the whole-volume Adam fit with 3D TV on the stick +
-ball diffusion workload (64^3 voxels, 96 measurements, 500 iterations,
-lambda 1e-3 on f, Da, De), voxel-iterations per second.
-
-Third leg (``sense``): image reconstruction with the same solver (one slice
-of a 6-echo, 32-coil, 256 x 256 CAIPI R_z = 9 acquisition, L1 loss with 2D
-TV, Adam 500 iterations), iterations per second.
+Other legs: the whole-volume Adam fit with 3D TV on the stick + ball
+diffusion workload (``adam``; 64^3 voxels, 96 measurements, 500 iterations);
+image reconstruction with the same solver (``sense``); the ensemble sampler,
+optimiser and regulariser variants (``next_rows``); and the serving loop
+(``serving``): a trace of 256 fit / MCMC jobs through the batching server and
+through the one-job-per-launch path, all jobs at once (saturated) and at the
+trace's Poisson arrival times (paced), with p50 / p99 latency.
 
 Each leg reports a roofline entry for its dominant kernel: algorithmic
 FLOPs (MH, ALU bound) or bytes (Adam+TV step, HBM bound) per launch divided
 by the launch time measured with HIP events on the launch stream.  The CPU
-baseline times the FP64 oracle (all host threads) on a bounded voxel sample
-of the MH workload.
+baseline times the FP64 oracle on a bounded voxel sample of the headline
+workload, on one thread and on every thread the process may use.
 """
 from __future__ import annotations
 
@@ -60,7 +61,7 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE likewise.  A figure holds only for the kernel sources it was
 # taken on: when their sha256 differs, `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "mh_chunk": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
+    "mh_chunk_cfg1": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
         "sha256": "fe6f1fb42a67f76b64a416d0457d3f1204c1d150362d1f4428856f8c579ab550",
         "read_bytes": 1595949552, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
@@ -97,23 +98,54 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def mh_leg(g, torch, steps, warmup):
+MH_WORKLOADS = {
+    # the whole-brain-sized 3-pool GRE volume: 240x240x180 grid, ellipsoid
+    # mask (1,199,888 voxels), SNR 50, 8 chains x 10,000, burn-in 1,000, thin 10
+    "cfg4": ("gre3 3-pool complex GRE MCMC, 240x240x180 grid, 1,199,888-voxel ellipsoid "
+             "mask, 24 echoes, SNR 50, 8 chains x 10000 iters, burn-in 1000, thin 10, "
+             "FP32 chains, FP64 moments", "cfg4", "CFG4_MCMC", 4),
+    # the 128x128x64 volume, SNR 100, 4 chains x 5,000, burn-in 500, thin 100
+    "cfg1": ("gre3 3-pool complex GRE MCMC, 128x128x64 voxels, 24 echoes, SNR 100, "
+             "4 chains x 5000 iters, burn-in 500, thin 100, FP32 chains, FP64 moments",
+             "cfg1", "CFG1_MCMC", 1),
+}
+
+
+def mh_draw(torch, g, which):
+    """The workload's draw, its data on the GPU (HIP forward + seeded noise)
+    and its model."""
     from paper_2511_22094_amd import synth
-    d = synth.cfg1()
-    kw = synth.CFG1_MCMC
+    _, fn, _, _ = MH_WORKLOADS[which]
+    d = getattr(synth, fn)()
     m = g.Model.from_acq("gre3", d.acq)
     dev = torch.device("cuda:0")
     nz, ny, nx = d.shape
     truth = torch.tensor(d.truth, dtype=torch.float32, device=dev)
     s = g.gc_model_forward(m, truth)
-    y = (s + d.sigma * torch.from_numpy(d.noise).to(dev)).reshape(48, nz, ny, nx).contiguous()
-    del s, truth
+    s += d.sigma * torch.from_numpy(d.noise).to(dev)
+    del truth
+    y = torch.zeros((48, nz * ny * nx), dtype=torch.float32, device=dev)
+    idx = torch.from_numpy(np.flatnonzero(d.mask.reshape(-1))).to(dev)
+    y[:, idx] = s
+    del s
+    return d, m, y.reshape(48, nz, ny, nx), torch.from_numpy(d.mask).to(dev), idx
+
+
+def mh_leg(g, torch, steps, warmup, which="cfg4", sample=None):
+    """Timed gc_mcmc calls over the whole volume, data and outputs resident on
+    the GPU; the mh_chunk launches timed with HIP events on their stream."""
+    from paper_2511_22094_amd import synth
+    _, _, kwname, seed = MH_WORKLOADS[which]
+    kw = getattr(synth, kwname)
+    d, m, y, mask, idx = mh_draw(torch, g, which)
+    dev = torch.device("cuda:0")
+    nz, ny, nx = d.shape
     step = synth.MH_STEP["gre3"]
     mean = torch.empty((9, nz, ny, nx), dtype=torch.float64, device=dev)
     std = torch.empty_like(mean)
 
     def run():
-        return g.gc_mcmc(m, y, None, d.lb, d.ub, sigma=d.sigma, step=step, seed=1,
+        return g.gc_mcmc(m, y, mask, d.lb, d.ub, sigma=d.sigma, step=step, seed=seed,
                          accept=False, out_mean=mean, out_std=std, **kw)
 
     for _ in range(warmup):
@@ -135,12 +167,17 @@ def mh_leg(g, torch, steps, warmup):
     launches_per_step = nl / steps
     units_per_launch = units / launches_per_step
     achieved = FLOP_PER_MH_STEP_GRE3 * units_per_launch / per_launch_s / 1e12
-    finite = bool(torch.isfinite(mean).all().item())
-    idx = torch.from_numpy(cpu_sample()).to(dev)
-    moments = (mean.reshape(9, -1)[:, idx].cpu().numpy(), std.reshape(9, -1)[:, idx].cpu().numpy())
+    finite = bool(torch.isfinite(mean.reshape(9, -1)[:, idx]).all().item())
+    moments = None
+    if sample is not None:
+        sidx = idx[torch.from_numpy(sample).to(dev)]
+        moments = (mean.reshape(9, -1)[:, sidx].cpu().numpy(),
+                   std.reshape(9, -1)[:, sidx].cpu().numpy())
+    del y, mean, std
+    torch.cuda.empty_cache()
     return dict(units=units, sec=sec, value=units / sec, per_launch_ms=per_launch_s * 1e3,
-                launches=launches_per_step, achieved_tflops=achieved, finite=finite,
-                n=n, workload=d, moments=moments)
+                launches=launches_per_step, units_per_launch=units_per_launch,
+                achieved_tflops=achieved, finite=finite, n=n, moments=moments, kw=kw)
 
 
 def adam_leg(g, torch, steps, warmup):
@@ -539,13 +576,17 @@ SERVE_MODELS = {
 
 
 def serve_trace_jobs(g, torch, n_jobs, vox_range, mcmc_iters, fit_iters, seed=3):
-    """Host-side job inputs of a serving trace (data made with the HIP forward)."""
+    """Host-side job inputs of a serving trace: parameters drawn per job on the
+    host (the trace's seed per job), data made with the HIP forward model and
+    noise from a seeded device generator, then copied to host memory (server
+    jobs carry host buffers)."""
     from paper_2511_22094_amd import synth
     trace = synth.serving_trace(seed, n_jobs, 20.0, vox_range, mcmc_iters, fit_iters)
     acqs = {"monoexp_t2s": synth.Acq(te=synth.echo_times(2.0, 4.0, 12)),
             "gre3": synth.Acq(te=synth.echo_times(2.0, 2.0, 24)),
             "dwi2": synth.dwi_acq(np.random.default_rng(1002))}
     models = {k: g.Model.from_acq(k, a) for k, a in acqs.items()}
+    dev = torch.device("cuda:0")
     jobs = []
     for j in trace:
         nx = 64
@@ -554,15 +595,32 @@ def serve_trace_jobs(g, torch, n_jobs, vox_range, mcmc_iters, fit_iters, seed=3)
         mask.reshape(-1)[: j.n_vox] = 1
         sigma = SERVE_MODELS[j.model]
         d = synth.make_draw(j.model, (1, ny, nx), j.seed, sigma, acq=acqs[j.model], mask=mask,
-                            block=4 if j.model == "dwi2" else 0)
+                            block=4 if j.model == "dwi2" else 0, noise=False)
         m = models[j.model]
-        s = g.gc_model_forward(m, torch.tensor(d.truth, dtype=torch.float32, device="cuda"))
-        y = (s + sigma * torch.from_numpy(d.noise).cuda()).cpu().numpy()
-        jobs.append((j, d, synth.scatter(y, mask), m))
+        s = g.gc_model_forward(m, torch.tensor(d.truth, dtype=torch.float32, device=dev))
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(j.seed)
+        s += sigma * torch.randn(s.shape, generator=gen, device=dev, dtype=torch.float32)
+        y = np.zeros((s.shape[0], 1, ny, nx), np.float32)
+        y.reshape(s.shape[0], -1)[:, : j.n_vox] = s.cpu().numpy()
+        del s
+        jobs.append((j, d, y, m))
     return jobs
 
 
+def _digest(r):
+    import hashlib
+    h = hashlib.sha1()
+    for k in ("mean", "std", "maps"):
+        if r.get(k) is not None:
+            h.update(np.ascontiguousarray(r[k]).tobytes())
+    return h.hexdigest()
+
+
 def serve_run(g, jobs, baseline, saturated, chunk=256):
+    """Submits the trace (paced by its arrival times, or all at once when
+    saturated), waits for every job, and returns throughput, latency
+    percentiles and a digest of every job's results."""
     from paper_2511_22094_amd import synth
     with g.Server(baseline=baseline, chunk_iters=chunk) as srv:
         ids = []
@@ -583,67 +641,122 @@ def serve_run(g, jobs, baseline, saturated, chunk=256):
                                      lam=1e-3 if j.tv else 0.0, tv_params=tv)
                 work = d.n * j.n_iter
             ids.append((jid, work))
-        for jid, _ in ids:
-            srv.wait(jid)
+        digests = []
+        finite = True
+        for k, (jid, _) in enumerate(ids):
+            r = srv.wait(jid)
+            digests.append(_digest(r))
+            finite &= all(bool(np.isfinite(r[x]).all()) for x in ("mean", "std", "maps")
+                          if r.get(x) is not None)
+            if (k + 1) % 32 == 0:
+                log(f"bench:   {k + 1}/{len(ids)} jobs done, {time.perf_counter() - t0:.1f} s")
         span = time.perf_counter() - t0
         st = srv.stats()
     total = sum(w for _, w in ids)
     return dict(makespan_s=span, value=total / span, p50_s=st["p50_latency_s"],
-                p99_s=st["p99_latency_s"], jobs=len(ids), voxel_iters=total)
+                p99_s=st["p99_latency_s"], jobs=len(ids), voxel_iters=total,
+                finite=finite), digests
 
 
-def serve_leg(g, torch, full=False):
-    if full:
-        jobs = serve_trace_jobs(g, torch, 256, (1e3, 1e6), (1000, 10000), (200, 500))
-    else:
-        jobs = serve_trace_jobs(g, torch, 64, (1e3, 1e5), (1000, 4000), (200, 500))
+SERVE_TRACES = {
+    # the serving workload: 256 jobs, voxels log-uniform in [1e3, 1e6], MCMC
+    # 1-8 chains x 1k-10k iterations, Adam 200-500 iterations
+    "full": (256, (1e3, 1e6), (1000, 10000), (200, 500)),
+    # a smaller trace of the same mix (voxels up to 1e5, MCMC up to 4k iterations)
+    "small": (64, (1e3, 1e5), (1000, 4000), (200, 500)),
+}
+
+
+def serve_leg(g, torch, trace="full", legs=("saturated", "paced")):
+    """Saturated legs (every job submitted at once) give the batching ratio at
+    full load; paced legs (Poisson arrivals at 20/s) give latency under the
+    trace's own load.  Batched and one-job-per-launch results are compared
+    job by job (digests of the result arrays)."""
+    n_jobs, vr, mi, fi = SERVE_TRACES[trace]
+    log(f"bench: serving trace {trace}: generating {n_jobs} jobs")
+    t0 = time.perf_counter()
+    jobs = serve_trace_jobs(g, torch, n_jobs, vr, mi, fi)
+    log(f"bench:   inputs ready in {time.perf_counter() - t0:.1f} s")
     out = {}
-    legs = [("batched", False, False), ("baseline", True, False)]
-    if os.environ.get("GACELLE_BENCH_SATURATED") == "1":
-        legs += [("batched_saturated", False, True), ("baseline_saturated", True, True)]
-    for name, base, sat in legs:
-        log(f"bench: serving {name}")
-        out[name] = serve_run(g, jobs, base, sat)
-        log(f"bench:   {out[name]}")
-    out["speedup"] = out["batched"]["value"] / out["baseline"]["value"]
-    if "batched_saturated" in out:
-        out["speedup_saturated"] = (out["batched_saturated"]["value"] /
-                                    out["baseline_saturated"]["value"])
-    out["trace"] = ("Poisson arrivals 20/s, %d jobs, models uniform over monoexp_t2s / gre3 / "
-                    "dwi2, voxels log-uniform in [%g, %g], 50/50 MCMC (1-8 chains) / Adam "
-                    "(TV on dwi2)" % (len(jobs), 1e3, 1e6 if full else 1e5))
+    same = True
+    for leg in legs:
+        sat = leg == "saturated"
+        res = {}
+        dig = {}
+        for mode in ("batched", "baseline"):
+            log(f"bench: serving {leg} {mode}")
+            res[mode], dig[mode] = serve_run(g, jobs, mode == "baseline", sat)
+            log(f"bench:   {res[mode]}")
+        res["speedup"] = res["batched"]["value"] / res["baseline"]["value"]
+        res["identical_results"] = dig["batched"] == dig["baseline"]
+        same &= res["identical_results"]
+        out[leg] = res
+    out["identical_results"] = same
+    out["trace"] = (f"Poisson arrivals 20/s, {n_jobs} jobs, models uniform over monoexp_t2s / "
+                    f"gre3 / dwi2, voxels log-uniform in [{vr[0]:g}, {vr[1]:g}], 50/50 MCMC "
+                    f"(1-8 chains, {mi[0]}-{mi[1]} iterations) / Adam ({fi[0]}-{fi[1]} "
+                    "iterations, TV on dwi2); saturated = all submitted at t = 0")
     return out
 
 
-def cpu_sample(sample_vox=6144):
-    """The fixed voxel sample of the MH workload that the CPU baseline runs."""
-    from paper_2511_22094_amd import synth
-    d = synth.cfg1()
-    rng = np.random.default_rng(1234)
-    return np.sort(rng.choice(d.n, sample_vox, replace=False))
+def host_cpu():
+    """Threads this process may run on, and the host CPU model (lscpu)."""
+    import subprocess
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env_omp = os.environ.get("OMP_NUM_THREADS")
+    if env_omp and env_omp.isdigit():
+        threads = min(threads, int(env_omp))
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return threads, model, os.cpu_count()
 
 
-def cpu_baseline(sample_vox=6144, gpu_moments=None):
-    """The FP64 oracle on a fixed voxel sample of the MH workload, all host
-    threads.  With gpu_moments = (mean, std) of the GPU run at the sampled
-    voxels ([P, sample]), also the GPU result's error against the oracle on
-    that sample (each side made its data with its own forward model)."""
+def cpu_sample(n, k, seed=1234):
+    """A fixed random sample of k of the workload's n (compacted) voxels."""
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
+
+
+def cpu_baseline(which="cfg4", per_thread=64, gpu_moments=None, sample=None):
+    """The FP64 oracle on a fixed voxel sample of the MH workload: once on one
+    thread (per_thread voxels) and once on every thread this process may use
+    (per_thread voxels per thread); the voxel indices of the sample key the
+    random streams, so the sampled chains are the ones the GPU runs.  With
+    gpu_moments = (mean, std) of the GPU run at `sample`, also the GPU result's
+    error against the oracle on that sample."""
     import oracle
     from paper_2511_22094_amd import synth
-    d = synth.cfg1()
-    kw = synth.CFG1_MCMC
-    idx = cpu_sample(sample_vox)
-    y = (oracle.forward("gre3", d.acq, d.truth[:, idx]) + d.sigma * d.noise[:, idx]).astype(np.float32)
-    threads = min(os.cpu_count() or 1, 16)
-    t0 = time.perf_counter()
-    ref = oracle.mh("gre3", d.acq, y, d.lb, d.ub, synth.MH_STEP["gre3"], d.sigma, 1, vidx=idx,
-                    n_threads=threads, **kw)
-    sec = time.perf_counter() - t0
-    units = sample_vox * kw["n_chains"] * kw["n_iter"]
-    out = dict(value=units / sec, unit="voxel-iterations/s", cores=threads, kind="oracle",
-               sample=f"{sample_vox} random voxels of the 128x128x64 gre3 volume, "
-                      f"{kw['n_chains']} chains x {kw['n_iter']} iterations, "
-                      f"FP64, {sec:.1f} s")
+    _, fn, kwname, seed = MH_WORKLOADS[which]
+    d = getattr(synth, fn)()
+    kw = getattr(synth, kwname)
+    threads, cpu_model, ncpu = host_cpu()
+    per_voxel = kw["n_chains"] * kw["n_iter"]
+
+    def run(idx, nt):
+        y = (oracle.forward("gre3", d.acq, d.truth[:, idx]) +
+             d.sigma * d.noise[:, idx]).astype(np.float32)
+        t0 = time.perf_counter()
+        ref = oracle.mh("gre3", d.acq, y, d.lb, d.ub, synth.MH_STEP["gre3"], d.sigma, seed,
+                        vidx=idx, n_threads=nt, **kw)
+        return ref, time.perf_counter() - t0
+
+    one = cpu_sample(d.n, per_thread, seed=4321)
+    _, t1 = run(one, 1)
+    alln = sample if sample is not None else cpu_sample(d.n, per_thread * threads)
+    ref, ta = run(alln, threads)
+    single = len(one) * per_voxel / t1
+    allc = len(alln) * per_voxel / ta
+    out = dict(value=allc, unit="voxel-iterations/s", cores=threads, kind="oracle",
+               sample=f"{len(alln)} random voxels of the {which} volume "
+                      f"({kw['n_chains']} chains x {kw['n_iter']} iterations each, FP64) on "
+                      f"{threads} threads, {ta:.1f} s",
+               single_thread={"value": single, "sample": f"{len(one)} voxels, {t1:.1f} s"},
+               host={"cpu_model": cpu_model, "cpu_count": ncpu, "threads_used": threads})
     err = None
     if gpu_moments is not None:
         gm, gs = gpu_moments
@@ -653,6 +766,7 @@ def cpu_baseline(sample_vox=6144, gpu_moments=None):
         err = {"what": "|GPU - oracle| of the posterior mean and SD, in units of the "
                        "oracle's posterior SD, over the sampled voxels x 9 parameters "
                        "(FP32 chains vs FP64 chains on the same random streams)",
+               "voxels": int(len(alln)),
                "mean_median": float(np.median(dm)), "mean_p99": float(np.quantile(dm, 0.99)),
                "sd_median": float(np.median(ds)), "sd_p99": float(np.quantile(ds, 0.99))}
     return out, err
@@ -719,14 +833,17 @@ def main():
     ap.add_argument("--no-sense", action="store_true")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the ensemble / optimiser / regulariser legs")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="serving leg on the full 256-job trace (voxels up to 1e6)")
+    ap.add_argument("--serve-trace", default="full", choices=sorted(SERVE_TRACES),
+                    help="serving trace: full (256 jobs, voxels up to 1e6) or small (64 jobs)")
+    ap.add_argument("--serve-legs", default="saturated,paced",
+                    help="comma list of saturated, paced")
     ap.add_argument("--bandwidth", action="store_true",
                     help="achievable HBM bandwidth of plain torch kernels (no headline line)")
     ap.add_argument("--sweep", action="store_true",
                     help="throughput against volume size per model (no headline line)")
     ap.add_argument("--profile-only", default=None,
-                    help="comma list of mh, adam, sense, ens, copy: run only these legs once each (no "
+                    help="comma list of mh (whole-brain volume), mh1 (128x128x64), adam, sense, ens, "
+                         "copy: run only these legs once each (no "
                          "warm-up, no headline line) for hardware counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -747,8 +864,8 @@ def main():
         rep = {}
         for leg in legs:
             log(f"bench: profile leg {leg}")
-            if leg == "mh":
-                r = mh_leg(g, torch, 1, 0)
+            if leg in ("mh", "mh1"):
+                r = mh_leg(g, torch, 1, 0, "cfg4" if leg == "mh" else "cfg1")
                 rep[leg] = {"launches": r["launches"], "per_launch_ms": r["per_launch_ms"]}
             elif leg == "adam":
                 r = adam_leg(g, torch, 1, 0)
@@ -765,10 +882,18 @@ def main():
                 raise SystemExit(f"unknown profile leg {leg!r}")
         print(json.dumps({"profile_only": rep}))
         return
-    log("bench: MH leg (gre3 128x128x64, 4 chains x 5000)")
-    mh = mh_leg(g, torch, args.steps, args.warmup)
+    from paper_2511_22094_amd import synth
+    n4 = int(synth.cfg4_mask().sum())
+    threads = host_cpu()[0]
+    sample = cpu_sample(n4, 64 * threads)
+    log("bench: MH leg (gre3 whole-brain volume, 1,199,888 voxels, 8 chains x 10000)")
+    mh = mh_leg(g, torch, args.steps, args.warmup, "cfg4", sample=sample)
     log(f"bench: MH {mh['value']:.3e} voxel-iter/s, {mh['sec']:.3f} s/step, "
         f"kernel {mh['per_launch_ms']:.2f} ms/launch")
+    log("bench: MH leg (gre3 128x128x64, 4 chains x 5000)")
+    mh1 = mh_leg(g, torch, max(1, min(args.steps, 5)), min(args.warmup, 1), "cfg1")
+    log(f"bench: MH {mh1['value']:.3e} voxel-iter/s, {mh1['sec']:.3f} s/step, "
+        f"kernel {mh1['per_launch_ms']:.2f} ms/launch")
     adam = None
     if not args.no_adam:
         log("bench: Adam+TV leg (dwi2 64^3, 500 iterations)")
@@ -789,12 +914,14 @@ def main():
             log(f"bench:   {k}: {v['value']:.3e} {v['unit']}, frac {v['roofline']['frac']:.3f}")
     serve = None
     if not args.no_serve:
-        serve = serve_leg(g, torch, args.serve_full)
+        serve = serve_leg(g, torch, args.serve_trace,
+                          tuple(x for x in args.serve_legs.split(",") if x))
     cpu = oracle_err = adam_err = sense_err = None
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        cpu, oracle_err = cpu_baseline(gpu_moments=mh["moments"])
-        log(f"bench: CPU {cpu['value']:.3e} voxel-iter/s on {cpu['cores']} threads")
+        cpu, oracle_err = cpu_baseline("cfg4", 64, gpu_moments=mh["moments"], sample=sample)
+        log(f"bench: CPU {cpu['value']:.3e} voxel-iter/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']:.3e} on one")
         if adam is not None:
             log("bench: Adam+TV error against the oracle (16^3)")
             adam_err = adam_oracle_error(g, torch)
@@ -821,18 +948,28 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "gre3 3-pool complex GRE MCMC, 128x128x64 voxels, 24 echoes, "
-                               "4 chains x 5000 iters, burn-in 500, thin 100, FP64 moments",
-                   "voxels": mh["n"], "chains": 4, "iterations": 5000},
+        "config": {"workload": MH_WORKLOADS["cfg4"][0], "voxels": mh["n"],
+                   "chains": mh["kw"]["n_chains"], "iterations": mh["kw"]["n_iter"],
+                   "burnin": mh["kw"]["burnin"], "thin": mh["kw"]["thin"]},
         "roofline": {"bound": "alu", "kernel": "mh_chunk<gre3,f32,24>",
                      "achieved": mh["achieved_tflops"], "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": mh["achieved_tflops"] / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic("mh_chunk"),
+                     "traffic": measured_traffic("mh_chunk_cfg4"),
                      "flop_per_step": FLOP_PER_MH_STEP_GRE3,
+                     "steps_per_launch": mh["units_per_launch"],
                      "launch_ms": mh["per_launch_ms"]},
         "cpu_baseline": cpu,
         "speedup_vs_cpu_oracle": (mh["value"] / cpu["value"]) if cpu else None,
         "oracle_error": oracle_err,
+        "mh_128x128x64": {
+            "value": mh1["value"], "unit": "voxel-iterations/s", "ms_per_step": mh1["sec"] * 1e3,
+            "workload": MH_WORKLOADS["cfg1"][0],
+            "roofline": {"bound": "alu", "kernel": "mh_chunk<gre3,f32,24>",
+                         "achieved": mh1["achieved_tflops"], "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": mh1["achieved_tflops"] / PEAK_FP32_TFLOPS,
+                         "traffic": measured_traffic("mh_chunk_cfg1"),
+                         "steps_per_launch": mh1["units_per_launch"],
+                         "launch_ms": mh1["per_launch_ms"]}},
     }
     if adam is not None:
         out["adam"] = {"value": adam["value"], "unit": "voxel-iterations/s",

@@ -228,6 +228,17 @@ int gc_fit_askadam(const gc_model *model, const gc_volume *data, const uint8_t *
  * ignored and the walkers play the role of chains in every output.
  * ------------------------------------------------------------------------ */
 enum { GC_X0_MIDPOINT = 0, GC_X0_UNIFORM = 1, GC_X0_GIVEN = 2 };
+
+/* Receiver of retained samples while the chains run (paper §2.2.2: the
+ * sampler keeps every thin-th state after burn-in).  Called on the calling
+ * thread, in order, once per delivery: `samples` is FP32 host memory owned by
+ * the library, [n_chains][k_count][n_params][n_masked], holding the retained
+ * draws k_first .. k_first + k_count - 1 (0-based, counted within this call)
+ * of every chain, in compacted voxel order; it is valid only during the call.
+ * A nonzero return stops the run: gc_mcmc then returns GC_E_CANCELLED and
+ * writes no output. */
+typedef int (*gc_sample_sink)(void *user, int k_first, int k_count, const float *samples,
+                              int64_t n_masked, int n_chains, int n_params);
 enum { GC_PREC_FP32 = 0, GC_PREC_FP64 = 1 };
 enum { GC_SAMPLER_MH = 0, GC_SAMPLER_ENSEMBLE = 1 };
 
@@ -250,13 +261,23 @@ typedef struct {
                                  t_start > 0, else overrides x0_mode */
     const double *init_logl;  /* [C][n_masked] their log-likelihoods (exec
                                  memory) or NULL = recomputed */
+    gc_sample_sink sample_sink;  /* streams the retained samples (out_samples must
+                                    then be NULL), or NULL */
+    void *sink_user;             /* passed to sample_sink */
+    size_t sink_bytes;           /* bytes per delivery (>= one draw of every chain
+                                    and voxel is always delivered); 0 = 256 MiB.
+                                    The library holds two device buffers and two
+                                    pinned host buffers of this size while the
+                                    call runs, and overlaps the copy of one
+                                    delivery with the chains' next steps. */
 } gc_mcmc_hyper;
 
 void gc_mcmc_defaults(gc_mcmc_hyper *h);
 int gc_burnin_from_ratio(double ratio, int n_iter);
 
 /* out_samples: [C][K][P][n_masked] retained samples in FP32 (exec memory) or
- * NULL; out_accept: [C][nz][ny][nx] accepted-move counts or NULL. */
+ * NULL (then hyper->sample_sink, if set, receives them as they are drawn);
+ * out_accept: [C][nz][ny][nx] accepted-move counts or NULL. */
 int gc_mcmc(const gc_model *model, const gc_volume *data, const uint8_t *mask,
             const gc_bounds *bounds, int n_chains, int n_iter, int burnin, int thin,
             const gc_mcmc_hyper *hyper, double *out_mean, double *out_std,
@@ -414,7 +435,7 @@ typedef struct {
     gc_bounds bounds;          /* x0_map, if any, host memory */
     gc_adam_hyper adam;        /* FIT: weights host memory; loss_history ignored */
     int n_chains, n_iter, burnin, thin;   /* MCMC */
-    gc_mcmc_hyper mcmc;        /* MCMC: weights host; final_* ignored */
+    gc_mcmc_hyper mcmc;        /* MCMC: weights host; final_* ignored; no sample sink */
     float *out_maps;           /* FIT: host [P][grid] */
     double *out_mean, *out_std;/* MCMC: host [P][grid] */
     int32_t *out_accept;       /* MCMC: host [C][grid] or NULL */

@@ -89,12 +89,34 @@ class gc_fit_report(ctypes.Structure):
     _fields_ = [("iters_run", c_int), ("final_loss", c_double), ("stop_reason", c_int)]
 
 
+# gc_sample_sink: int (*)(void *user, int k_first, int k_count, const float *samples,
+#                         int64_t n_masked, int n_chains, int n_params)
+SAMPLE_SINK = ctypes.CFUNCTYPE(c_int, c_void_p, c_int, c_int, ctypes.POINTER(ctypes.c_float),
+                               c_int64, c_int, c_int)
+
+
 class gc_mcmc_hyper(ctypes.Structure):
     _fields_ = [("sigma", c_double), ("step", c_void_p), ("seed", c_uint64), ("x0_mode", c_int),
                 ("weights", c_void_p), ("precision", c_int), ("sampler", c_int),
                 ("n_walkers", c_int), ("stretch", c_double), ("chunk_iters", c_int),
                 ("final_state", c_void_p), ("final_logl", c_void_p), ("t_start", c_int),
-                ("init_state", c_void_p), ("init_logl", c_void_p)]
+                ("init_state", c_void_p), ("init_logl", c_void_p),
+                ("sample_sink", SAMPLE_SINK), ("sink_user", c_void_p), ("sink_bytes", c_size_t)]
+
+
+def _sink(fn):
+    """Wraps fn(k_first, samples) -- samples a float32 numpy view [C, k, P, n]
+    valid only during the call -- as a gc_sample_sink; fn returning False (or
+    raising) stops the run."""
+    def cb(_user, k_first, k_count, ptr, n, C, P):
+        try:
+            arr = np.ctypeslib.as_array(ptr, shape=(C, k_count, P, n))
+            return 1 if fn(int(k_first), arr) is False else 0
+        except Exception:   # noqa: BLE001 -- any failure stops the run
+            import traceback
+            traceback.print_exc()
+            return 1
+    return SAMPLE_SINK(cb)
 
 
 class gc_sense_problem(ctypes.Structure):
@@ -315,6 +337,7 @@ def gc_version() -> str:
     return _L.gc_version().decode()
 
 
+
 def gc_burnin_from_ratio(ratio: float, n_iter: int) -> int:
     return int(_L.gc_burnin_from_ratio(ratio, n_iter))
 
@@ -399,12 +422,18 @@ def gc_mcmc(model: Model, y, mask, lb, ub, n_chains, n_iter, burnin, thin, *, si
             step=None, seed=0, x0=None, x0_map=None, x0_mode="midpoint", weights=None,
             precision="fp32", sampler="mh", n_walkers=50, stretch=2.0, chunk_iters=0,
             samples=False, accept=True, final_state=False, out_mean=None, out_std=None,
-            t_start=0, init_state=None, init_logl=None):
+            t_start=0, init_state=None, init_logl=None, sample_sink=None, sink_bytes=0):
     """Returns dict(mean, std [P, nz, ny, nx] float64, accept [C, nz, ny, nx],
     samples [C, K, P, n_masked] float32 or None, final_state [P, C, n], final_logl [C, n]).
 
     Resume: t_start > 0 with init_state [P, C, n] (and init_logl [C, n]), e.g. the
-    final_state / final_logl of a call that ran up to step t_start."""
+    final_state / final_logl of a call that ran up to step t_start.
+
+    sample_sink: fn(k_first, samples) receiving the retained samples while the
+    chains run, in deliveries of at most sink_bytes (0 = 256 MiB): samples is a
+    float32 view [C, k, P, n_masked] of host memory valid only during the call
+    (copy what you keep); returning False stops the run (GcError
+    GC_E_CANCELLED).  Not with samples=True."""
     a = _Args()
     nx, ny, nz = _shape3(y, model)
     vol = gc_volume(nx, ny, nz, a.ptr(y, np.float32))
@@ -429,6 +458,11 @@ def gc_mcmc(model: Model, y, mask, lb, ub, n_chains, n_iter, burnin, thin, *, si
     h.t_start = int(t_start)
     h.init_state = a.ptr(init_state, np.float64)
     h.init_logl = a.ptr(init_logl, np.float64)
+    if sample_sink is not None:
+        cb = _sink(sample_sink)
+        a.keep.append(cb)
+        h.sample_sink = cb
+        h.sink_bytes = int(sink_bytes)
     C = n_walkers if sampler == "ensemble" else n_chains
     K = (n_iter - burnin) // thin - (max(t_start - burnin, 0) // thin)
     if mask is None:

@@ -73,6 +73,16 @@ Scratch::~Scratch() {
 hipError_t Scratch::alloc(void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
+    if (fixed) {
+        const size_t b = (bytes + 255) / 256 * 256;
+        if (used + b > cap) {
+            short_by += used + b - cap;
+            return hipErrorOutOfMemory;
+        }
+        *p = fixed + used;
+        used += b;
+        return hipSuccess;
+    }
     hipError_t e = arena ? arena->alloc(p, bytes) : hipMallocAsync(p, bytes, s);
     if (e == hipSuccess) ptrs.push_back(*p);
     return e;
@@ -396,6 +406,8 @@ int fill_mh_job(const gc_model* m, const gc_bounds* b, const gc_mcmc_hyper* h, i
     auto kept_before = [&](int T) { return T > burnin ? (T - burnin) / thin : 0; };
     J->k_base = kept_before(h->t_start);
     J->K = kept_before(n_iter) - J->k_base;
+    J->s_base = J->k_base;   // a sample buffer holds all of this call's draws
+    J->s_K = J->K;
     J->x0_mode = h->x0_mode;
     for (int p = 0; p < m->P; ++p) {
         const double lo = b->lb[p], hi = b->ub[p];
@@ -837,13 +849,67 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
     GC_GUARD_END
 }
 
+}  // extern "C"
+
+namespace gc {
+
 // ------------------------------------------------------------------ MCMC
-int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
-            const gc_bounds* bounds, int n_chains, int n_iter, int burnin, int thin,
-            const gc_mcmc_hyper* hyper, double* out_mean, double* out_std, float* out_samples,
-            int32_t* out_accept, const gc_exec* exec) {
-    GC_GUARD_BEGIN
-    clear_error();
+// Model acquisition tables copied into a caller-provided scratch region (the
+// allocation-free entry point), with the same layout as model_acq's.
+static int model_acq_into(const gc_model* m, Scratch& sc, AcqDev* out) {
+    const int M = m->M;
+    std::vector<float> f(5 * M, 0.f);
+    std::vector<double> d(5 * M, 0.0);
+    for (int j = 0; j < M; ++j) {
+        if (!m->te.empty()) {
+            f[j] = (float)m->te[j];
+            d[j] = m->te[j];
+        }
+        if (!m->bval.empty()) {
+            f[M + j] = (float)(m->bval[j] * 1e-3);
+            d[M + j] = m->bval[j] * 1e-3;
+            for (int k = 0; k < 3; ++k) {
+                f[2 * M + 3 * j + k] = (float)m->bvec[3 * j + k];
+                d[2 * M + 3 * j + k] = m->bvec[3 * j + k];
+            }
+        }
+    }
+    std::vector<int32_t> run_end;
+    for (int j = 1; j < M; ++j)
+        if (!m->bval.empty() && m->bval[j] != m->bval[j - 1]) run_end.push_back(j);
+    run_end.push_back(M);
+    float* fp = nullptr;
+    double* dp = nullptr;
+    int32_t* rp = nullptr;
+    GC_TRY_HIP(sc.alloc_n(&fp, f.size()));
+    GC_TRY_HIP(sc.alloc_n(&dp, d.size()));
+    GC_TRY_HIP(sc.alloc_n(&rp, run_end.size()));
+    GC_TRY_HIP(hipMemcpyAsync(fp, f.data(), f.size() * 4, hipMemcpyHostToDevice, sc.s));
+    GC_TRY_HIP(hipMemcpyAsync(dp, d.data(), d.size() * 8, hipMemcpyHostToDevice, sc.s));
+    GC_TRY_HIP(hipMemcpyAsync(rp, run_end.data(), run_end.size() * 4, hipMemcpyHostToDevice, sc.s));
+    GC_TRY_HIP(hipStreamSynchronize(sc.s));   // the host vectors go out of scope
+    AcqDev a{};
+    a.te = fp;
+    a.bval = fp + M;
+    a.bvec = fp + 2 * M;
+    a.te_d = dp;
+    a.bval_d = dp + M;
+    a.bvec_d = dp + 2 * M;
+    a.M = M;
+    a.uniform = m->uniform ? 1 : 0;
+    a.te0 = (float)m->te0;
+    a.dte = (float)m->dte;
+    a.te0_d = m->te0;
+    a.dte_d = m->dte;
+    a.run_end = rp;
+    a.nrun = (int)run_end.size();
+    *out = a;
+    return GC_OK;
+}
+
+int mcmc_validate(const gc_model* model, const gc_volume* data, const gc_bounds* bounds,
+                  int* n_chains, int n_iter, int burnin, int thin, const gc_mcmc_hyper* hyper,
+                  const double* out_mean, const double* out_std, const float* out_samples) {
     int rc;
     GC_REQUIRE(model && hyper && out_mean && out_std, GC_E_INVAL, "null argument");
     if ((rc = validate_volume(model, data))) return rc;
@@ -853,9 +919,9 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
     if (ens) {
         GC_REQUIRE(hyper->n_walkers >= 4 && hyper->n_walkers % 2 == 0 && hyper->n_walkers <= 512,
                    GC_E_INVAL, "n_walkers must be even, in 4..512");
-        n_chains = hyper->n_walkers;
+        *n_chains = hyper->n_walkers;
     }
-    GC_REQUIRE(n_chains >= 1 && n_chains <= 65535, GC_E_INVAL, "n_chains must be in 1..65535");
+    GC_REQUIRE(*n_chains >= 1 && *n_chains <= 65535, GC_E_INVAL, "n_chains must be in 1..65535");
     GC_REQUIRE(n_iter >= 1 && burnin >= 0 && burnin < n_iter && thin >= 1, GC_E_INVAL,
                "need n_iter >= 1, 0 <= burnin < n_iter, thin >= 1");
     GC_REQUIRE(hyper->t_start >= 0 && hyper->t_start < n_iter, GC_E_INVAL,
@@ -873,13 +939,51 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
     GC_REQUIRE(hyper->precision == GC_PREC_FP32 || hyper->precision == GC_PREC_FP64, GC_E_INVAL,
                "precision must be GC_PREC_FP32 or GC_PREC_FP64");
     GC_REQUIRE(hyper->x0_mode >= 0 && hyper->x0_mode <= 2, GC_E_INVAL, "bad x0_mode");
+    GC_REQUIRE(!(hyper->sample_sink && out_samples), GC_E_INVAL,
+               "give either out_samples or a sample sink, not both");
+    return GC_OK;
+}
+
+namespace {
+
+// Pinned host staging, copy stream and events of a sample sink; released by
+// the destructor (after the streams have been synchronised by the caller).
+struct SinkRes {
+    void* pin[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr}, copied[2] = {nullptr, nullptr};
+    hipStream_t cs = nullptr;
+    ~SinkRes() {
+        if (cs) {
+            (void)hipStreamSynchronize(cs);
+            (void)hipStreamDestroy(cs);
+        }
+        for (int i = 0; i < 2; ++i) {
+            if (pin[i]) (void)hipHostFree(pin[i]);
+            if (done[i]) (void)hipEventDestroy(done[i]);
+            if (copied[i]) (void)hipEventDestroy(copied[i]);
+        }
+    }
+};
+
+}  // namespace
+
+// The body of gc_mcmc and of its allocation-free variant: all device memory
+// comes from `sc`; with noalloc the model tables are staged into it too and
+// nothing else is allocated (no free-memory query, no timing events).
+int mcmc_impl(const gc_model* model, const gc_volume* data, const uint8_t* mask,
+              const gc_bounds* bounds, int n_chains, int n_iter, int burnin, int thin,
+              const gc_mcmc_hyper* hyper, double* out_mean, double* out_std, float* out_samples,
+              int32_t* out_accept, DeviceScope& ds, Scratch& sc, bool noalloc) {
+    int rc;
+    const bool ens = hyper->sampler == GC_SAMPLER_ENSEMBLE;
     const bool fp64 = hyper->precision == GC_PREC_FP64;
-    DeviceScope ds;
-    if ((rc = ds.open(exec))) return rc;
     const hipStream_t s = ds.stream;
-    Scratch sc(s);
     AcqDev acq;
-    if ((rc = model_acq(model, ds.dev, &acq))) return rc;
+    if (noalloc) {
+        if ((rc = model_acq_into(model, sc, &acq))) return rc;
+    } else if ((rc = model_acq(model, ds.dev, &acq))) {
+        return rc;
+    }
     Packed pk;
     const float* x0map = hyper->x0_mode == GC_X0_GIVEN ? bounds->x0_map : nullptr;
     if ((rc = pack_problem(sc, model, data, mask, hyper->weights, x0map, ds.mem_kind, &pk)))
@@ -906,11 +1010,12 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
     }
     const size_t rs = fp64 ? sizeof(double) : sizeof(float);
     const size_t nl1 = (size_t)std::max<int64_t>(NL, 1);
-    // footprint check against free device memory
-    size_t freeb = 0, totalb = 0;
-    GC_TRY_HIP(hipMemGetInfo(&freeb, &totalb));
-    const size_t need = nl1 * (P * rs + rs + 4 + 2 * P * sizeof(double));
-    GC_REQUIRE(need < freeb, GC_E_NOMEM, "chain state needs %zu bytes, %zu free", need, freeb);
+    if (!noalloc) {   // footprint check against free device memory
+        size_t freeb = 0, totalb = 0;
+        GC_TRY_HIP(hipMemGetInfo(&freeb, &totalb));
+        const size_t need = nl1 * (P * rs + rs + 4 + 2 * P * sizeof(double));
+        GC_REQUIRE(need < freeb, GC_E_NOMEM, "chain state needs %zu bytes, %zu free", need, freeb);
+    }
     GC_TRY_HIP(sc.alloc(&J.th, nl1 * P * rs));
     GC_TRY_HIP(sc.alloc(&J.ll, nl1 * rs));
     GC_TRY_HIP(sc.alloc_n(&J.acc, nl1));
@@ -922,18 +1027,60 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
     J.samples = dsamp;
     std::vector<MhJob> jobs;
     std::vector<BlkMap> hmap, emap;
+    std::vector<int> delivery;   // sink: delivery index of each launch (-1 = none)
     double *mean_c = nullptr, *std_c = nullptr;
     GC_TRY_HIP(sc.alloc_n(&mean_c, (size_t)std::max<int64_t>(n, 1) * P));
     GC_TRY_HIP(sc.alloc_n(&std_c, (size_t)std::max<int64_t>(n, 1) * P));
+    SinkRes sink;
+    const bool streaming = hyper->sample_sink != nullptr && n > 0;
+    int kc = 0;                  // retained draws per chain per delivery
+    float* sbuf[2] = {nullptr, nullptr};
     if (n > 0) {
         const int chunk = hyper->chunk_iters > 0 ? hyper->chunk_iters : 1000;
         const int t_first = hyper->t_start;
-        const int nck = (n_iter - t_first + chunk - 1) / chunk;
-        jobs.assign(nck, J);
-        for (int c = 0; c < nck; ++c) {
-            jobs[c].t0 = t_first + c * chunk;
-            jobs[c].t1 = std::min(n_iter, t_first + (c + 1) * chunk);
+        if (!streaming) {
+            const int nck = (n_iter - t_first + chunk - 1) / chunk;
+            jobs.assign(nck, J);
+            for (int c = 0; c < nck; ++c) {
+                jobs[c].t0 = t_first + c * chunk;
+                jobs[c].t1 = std::min(n_iter, t_first + (c + 1) * chunk);
+            }
+        } else {
+            // Deliveries of kc retained draws per chain ([C][kc][P][n] FP32, at
+            // most sink_bytes, at least one draw); delivery j holds the draws
+            // k_base + j kc + 1 .. of this call, retained at steps
+            // t = burnin - 1 + k thin.  Its launches end right after its last
+            // draw (at most chunk steps each), and it is written into one of two
+            // device buffers while the other is copied to the host.
+            const size_t per_draw = (size_t)C * P * (size_t)n * sizeof(float);
+            const size_t cap = hyper->sink_bytes > 0 ? hyper->sink_bytes : ((size_t)256 << 20);
+            kc = (int)std::max<size_t>(1, std::min<size_t>((size_t)K, cap / per_draw));
+            const int nd = (K + kc - 1) / kc;
+            int t = t_first;
+            for (int j = 0; j < nd; ++j) {
+                const int k_lo = J.k_base + j * kc;                 // draws before this delivery
+                const int k_hi = J.k_base + std::min(K, (j + 1) * kc);
+                const int t_end = j == nd - 1 ? n_iter : burnin - 1 + k_hi * thin + 1;
+                for (; t < t_end; t = std::min(t_end, t + chunk)) {
+                    MhJob q = J;
+                    q.t0 = t;
+                    q.t1 = std::min(t_end, t + chunk);
+                    q.s_base = k_lo;
+                    q.s_K = k_hi - k_lo;
+                    jobs.push_back(q);
+                    delivery.push_back(j);
+                }
+            }
+            for (int b = 0; b < 2 && b < nd; ++b) {
+                GC_TRY_HIP(sc.alloc_n(&sbuf[b], (size_t)C * kc * P * (size_t)n));
+                GC_TRY_HIP(hipHostMalloc(&sink.pin[b], per_draw * kc, hipHostMallocDefault));
+                GC_TRY_HIP(hipEventCreateWithFlags(&sink.done[b], hipEventDisableTiming));
+                GC_TRY_HIP(hipEventCreateWithFlags(&sink.copied[b], hipEventDisableTiming));
+            }
+            GC_TRY_HIP(hipStreamCreateWithFlags(&sink.cs, hipStreamNonBlocking));
+            for (size_t i = 0; i < jobs.size(); ++i) jobs[i].samples = sbuf[delivery[i] % 2];
         }
+        const int nck = (int)jobs.size();
         MhJob* djob = nullptr;
         GC_TRY_HIP(sc.alloc_n(&djob, (size_t)nck));
         GC_TRY_HIP(hipMemcpyAsync(djob, jobs.data(), nck * sizeof(MhJob), hipMemcpyHostToDevice, s));
@@ -946,6 +1093,8 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
         BlkMap* dmap = nullptr;
         GC_TRY_HIP(sc.alloc_n(&dmap, hmap.size()));
         GC_TRY_HIP(hipMemcpyAsync(dmap, hmap.data(), hmap.size() * sizeof(BlkMap), hipMemcpyHostToDevice, s));
+        const BlkMap* cmap = dmap;   // chunk launches: lanes, or voxel groups for the ensemble
+        int cblk = (int)nblk;
         if (ens) {
             GC_TRY_HIP(ens_init(model->kind, fp64, djob, dmap, (int)nblk, s));
             // chunks: blocks cover groups of vpb voxels with all their walkers
@@ -957,28 +1106,70 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
             GC_TRY_HIP(sc.alloc_n(&demap, emap.size()));
             GC_TRY_HIP(hipMemcpyAsync(demap, emap.data(), emap.size() * sizeof(BlkMap),
                                       hipMemcpyHostToDevice, s));
-            LaunchTimer tm("ens_chunk", s);
-            for (int c = 0; c < nck; ++c) {
-                tm.begin();
-                GC_TRY_HIP(ens_chunk_walkers(model->kind, fp64, djob + c, demap, (int)eblk, C,
-                                             model->Meff, s));
-                tm.end();
-            }
-            GC_TRY_HIP(hipStreamSynchronize(s));
-            tm.flush();
+            cmap = demap;
+            cblk = (int)eblk;
         } else {
             GC_TRY_HIP(mh_init(model->kind, fp64, djob, dmap, (int)nblk, s));
-            const int maxm = mh_pick_variant(model->kind, model->M, model->uniform ? 1 : 0);
-            LaunchTimer tm("mh_chunk", s);
-            for (int c = 0; c < nck; ++c) {
-                tm.begin();
-                GC_TRY_HIP(mh_chunk(model->kind, fp64, maxm, djob + c, dmap, (int)nblk, C, model->Meff, s));
-                tm.end();
+        }
+        const int maxm = mh_pick_variant(model->kind, model->M, model->uniform ? 1 : 0);
+        LaunchTimer tm(ens ? "ens_chunk" : "mh_chunk", s);
+        const bool timed = !noalloc && timing_on();
+        auto launch = [&](int c) -> int {
+            if (timed) tm.begin();
+            if (ens)
+                GC_TRY_HIP(ens_chunk_walkers(model->kind, fp64, djob + c, cmap, cblk, C,
+                                             model->Meff, s));
+            else
+                GC_TRY_HIP(mh_chunk(model->kind, fp64, maxm, djob + c, cmap, cblk, C, model->Meff, s));
+            if (timed) tm.end();
+            return GC_OK;
+        };
+        if (!streaming) {
+            for (int c = 0; c < nck; ++c)
+                if ((rc = launch(c))) return rc;
+        } else {
+            // delivery j: launches into buffer j % 2 (after the copy of delivery
+            // j - 2 has read it), then an event; the host hands delivery j - 2
+            // to the sink (its pinned slot is then free) and queues the copy of
+            // delivery j on the copy stream
+            const size_t per_draw = (size_t)C * P * (size_t)n * sizeof(float);
+            const int nd = delivery.back() + 1;
+            auto deliver = [&](int j) -> int {
+                const int b = j % 2;
+                GC_TRY_HIP(hipEventSynchronize(sink.copied[b]));
+                const int k_first = j * kc;
+                const int k_cnt = std::min(K, (j + 1) * kc) - k_first;
+                const int r = hyper->sample_sink(hyper->sink_user, k_first, k_cnt,
+                                                 (const float*)sink.pin[b], n, C, P);
+                GC_REQUIRE(r == 0, GC_E_CANCELLED, "the sample sink stopped the run (%d)", r);
+                return GC_OK;
+            };
+            int c = 0;
+            for (int j = 0; j < nd; ++j) {
+                const int b = j % 2;
+                if (j >= 2) GC_TRY_HIP(hipStreamWaitEvent(s, sink.copied[b], 0));
+                for (; c < nck && delivery[c] == j; ++c)
+                    if ((rc = launch(c))) return rc;
+                GC_TRY_HIP(hipEventRecord(sink.done[b], s));
+                if (j >= 2 && (rc = deliver(j - 2))) {
+                    (void)hipStreamSynchronize(s);
+                    return rc;
+                }
+                const int k_cnt = std::min(K, (j + 1) * kc) - j * kc;
+                GC_TRY_HIP(hipStreamWaitEvent(sink.cs, sink.done[b], 0));
+                GC_TRY_HIP(hipMemcpyAsync(sink.pin[b], sbuf[b], per_draw * k_cnt,
+                                          hipMemcpyDeviceToHost, sink.cs));
+                GC_TRY_HIP(hipEventRecord(sink.copied[b], sink.cs));
             }
-            if (timing_on()) {
-                GC_TRY_HIP(hipStreamSynchronize(s));
-                tm.flush();
-            }
+            for (int j = std::max(0, nd - 2); j < nd; ++j)
+                if ((rc = deliver(j))) {
+                    (void)hipStreamSynchronize(s);
+                    return rc;
+                }
+        }
+        if (timed) {
+            GC_TRY_HIP(hipStreamSynchronize(s));
+            tm.flush();
         }
         GC_TRY_HIP(mh_finalize(fp64, djob, dmap + nblk, (int)vblk, mean_c, std_c, s));
     }
@@ -1020,6 +1211,27 @@ int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
     }
     GC_TRY_HIP(hipStreamSynchronize(s));
     return GC_OK;
+}
+
+}  // namespace gc
+
+extern "C" {
+
+int gc_mcmc(const gc_model* model, const gc_volume* data, const uint8_t* mask,
+            const gc_bounds* bounds, int n_chains, int n_iter, int burnin, int thin,
+            const gc_mcmc_hyper* hyper, double* out_mean, double* out_std, float* out_samples,
+            int32_t* out_accept, const gc_exec* exec) {
+    GC_GUARD_BEGIN
+    clear_error();
+    int rc;
+    if ((rc = mcmc_validate(model, data, bounds, &n_chains, n_iter, burnin, thin, hyper, out_mean,
+                            out_std, out_samples)))
+        return rc;
+    DeviceScope ds;
+    if ((rc = ds.open(exec))) return rc;
+    Scratch sc(ds.stream);
+    return mcmc_impl(model, data, mask, bounds, n_chains, n_iter, burnin, thin, hyper, out_mean,
+                     out_std, out_samples, out_accept, ds, sc, false);
     GC_GUARD_END
 }
 

@@ -253,7 +253,8 @@ __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restri
                         mu[h][p] += d * inv;
                         m2[h][p] += d * (x - mu[h][p]);
                         if (J.samples)
-                            J.samples[(((int64_t)k * J.K + (kk - 1)) * P + p) * n + v] = (float)x;
+                            J.samples[(((int64_t)k * J.s_K + (kk - 1 - J.s_base)) * P + p) * n +
+                                      v] = (float)x;
                     }
                 }
             }

@@ -29,6 +29,8 @@ struct MhJob {
     int t0, t1;              // iterations of this launch
     int burnin, thin, K;     // retention; K = samples per chain in this call
     int k_base;              // samples retained before this call's first step
+    int s_base, s_K;         // sample buffer: retained draws s_base + 1 .. s_base + s_K
+                             // (counted from step 0) of every chain, [C][s_K][P][n]
     int x0_mode;
     const double* init_state;   // [P][C n] start states (resume) or nullptr
     const double* init_logl;    // [C][n] their log-likelihoods or nullptr

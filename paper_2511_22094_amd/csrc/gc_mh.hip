@@ -244,9 +244,10 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
                 m2[p] += d * (x - mu[p]);
             }
             if (J.samples) {
+                const int ks = (t - B + 1) / thin - J.s_base - 1;   // slot in the buffer
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    J.samples[(((int64_t)c * J.K + (k - 1)) * P + p) * n + v] = (float)th[p];
+                    J.samples[(((int64_t)c * J.s_K + ks) * P + p) * n + v] = (float)th[p];
             }
         }
     }

@@ -93,11 +93,16 @@ struct DevArena {
 };
 
 // Scratch allocations released at scope exit: stream-ordered on `s`
-// (synchronous entry points, one stream), or from an arena (server).
+// (synchronous entry points, one stream), from an arena (server), or carved
+// in order from a fixed region the caller owns (allocation-free entry
+// points: nothing is allocated or released; a request past the region's end
+// fails with hipErrorOutOfMemory and is remembered in `short_by`).
 struct Scratch {
     hipStream_t s = nullptr;
     DevArena* arena = nullptr;
     std::vector<void*> ptrs;
+    char* fixed = nullptr;
+    size_t cap = 0, used = 0, short_by = 0;
     explicit Scratch(hipStream_t st, DevArena* a = nullptr) : s(st), arena(a) {}
     ~Scratch();
     hipError_t alloc(void** p, size_t bytes);
@@ -152,5 +157,15 @@ int fill_fit_job(const gc_model* m, const gc_bounds* b, const gc_adam_hyper* h, 
 
 void mempool_setup(int device);
 double now_seconds();
+
+// MCMC (gc_mcmc and its allocation-free variant): argument checks, then the
+// whole call with every device allocation drawn from `sc`.
+int mcmc_validate(const gc_model* model, const gc_volume* data, const gc_bounds* bounds,
+                  int* n_chains, int n_iter, int burnin, int thin, const gc_mcmc_hyper* hyper,
+                  const double* out_mean, const double* out_std, const float* out_samples);
+int mcmc_impl(const gc_model* model, const gc_volume* data, const uint8_t* mask,
+              const gc_bounds* bounds, int n_chains, int n_iter, int burnin, int thin,
+              const gc_mcmc_hyper* hyper, double* out_mean, double* out_std, float* out_samples,
+              int32_t* out_accept, DeviceScope& ds, Scratch& sc, bool noalloc);
 
 }  // namespace gc

@@ -963,6 +963,8 @@ int gc_submit(gc_server* S, const gc_job* job, uint64_t* job_id) {
             GC_REQUIRE(h.sigma > 0, GC_E_INVAL, "sigma must be > 0");
             GC_REQUIRE(h.t_start == 0 && !h.init_state, GC_E_INVAL,
                        "resume (t_start, init_state) is a gc_mcmc option, not a server job's");
+            GC_REQUIRE(!h.sample_sink, GC_E_INVAL,
+                       "server jobs return moments only; stream samples with gc_mcmc");
             if (h.step) J->step.assign(h.step, h.step + P);
         } else if (job->kind == GC_JOB_FIT) {
             const gc_adam_hyper& h = job->adam;

@@ -227,7 +227,9 @@ def default_acq(model: str, rng=None) -> Acq:
 
 
 def make_draw(model: str, shape, seed: int, sigma: float, acq: Optional[Acq] = None,
-              mask: Optional[np.ndarray] = None, block: int = 0) -> Draw:
+              mask: Optional[np.ndarray] = None, block: int = 0, noise: bool = True) -> Draw:
+    """Truth drawn from `seed`; with noise=False no noise is drawn (the caller
+    makes its own) and Draw.noise is None."""
     rng = np.random.default_rng(seed)
     if acq is None:
         acq = default_acq(model, rng)
@@ -245,9 +247,9 @@ def make_draw(model: str, shape, seed: int, sigma: float, acq: Optional[Acq] = N
         block_ids = ids[mask.astype(bool)]
     truth = np.ascontiguousarray(draw_truth(model, rng, n, block_ids))
     me = meas_eff(model, acq.n_meas)
-    noise = rng.standard_normal((me, n), dtype=np.float32)
+    nz_ = rng.standard_normal((me, n), dtype=np.float32) if noise else None
     lb, ub = bounds(model)
-    return Draw(model, acq, tuple(shape), mask, truth, noise, float(sigma), lb, ub, seed)
+    return Draw(model, acq, tuple(shape), mask, truth, nz_, float(sigma), lb, ub, seed)
 
 
 # ---------------------------------------------------------------------------

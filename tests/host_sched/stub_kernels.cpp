@@ -72,10 +72,12 @@ void mh_arrays(int kind, bool fp64, const MhJob& J, uint64_t seq, const char* k,
         }
     }
     if (chunk && J.samples) {
-        dev_ok(J.samples, J.samples, (size_t)J.C * J.K * P * n * 4, seq, k, "samples");
-        if (kept_before(J.t1, J.burnin, J.thin) - J.k_base > J.K)
-            violation("%s: steps [%d, %d) retain past the %d samples per chain of the buffer", k,
-                      J.t0, J.t1, J.K);
+        dev_ok(J.samples, J.samples, (size_t)J.C * J.s_K * P * n * 4, seq, k, "samples");
+        // draws retained in [t0, t1) must fall in the buffer's window
+        const int lo = kept_before(J.t0, J.burnin, J.thin), hi = kept_before(J.t1, J.burnin, J.thin);
+        if (hi > lo && (lo < J.s_base || hi > J.s_base + J.s_K))
+            violation("%s: steps [%d, %d) retain draws %d..%d outside the buffer's %d..%d", k,
+                      J.t0, J.t1, lo + 1, hi, J.s_base + 1, J.s_base + J.s_K);
     }
 }
 
@@ -220,9 +222,13 @@ hipError_t ens_chunk_walkers(int kind, bool fp64, const MhJob* jobs, const BlkMa
             [&](const MhJob& J) {
                 mh_arrays(kind, fp64, J, seq, k, false, false);
                 if (J.samples) {
-                    dev_ok(J.samples, J.samples, (size_t)J.C * J.K * P * J.n * 4, seq, k, "samples");
-                    if (kept_before(J.t1, J.burnin, J.thin) > J.K)
-                        violation("%s: steps up to %d retain past %d samples", k, J.t1, J.K);
+                    dev_ok(J.samples, J.samples, (size_t)J.C * J.s_K * P * J.n * 4, seq, k,
+                           "samples");
+                    const int lo = kept_before(J.t0, J.burnin, J.thin);
+                    const int hi = kept_before(J.t1, J.burnin, J.thin);
+                    if (hi > lo && (lo < J.s_base || hi > J.s_base + J.s_K))
+                        violation("%s: draws %d..%d outside the buffer's %d..%d", k, lo + 1, hi,
+                                  J.s_base + 1, J.s_base + J.s_K);
                 }
             });
     });
