@@ -53,6 +53,16 @@ FLOP_PER_MH_STEP_GRE3 = 18 + 35 + 2 + 30 + 672 + 1      # = 758
 BYTES_PER_ADAM_TV_VOXEL_ITER = 96 * 4 + 2 * 5 * 4 + 2 * 2 * 5 * 4 + 6 * 4   # = 528
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# The instruction mix of one gre3 MH step (from the kernel's ISA, confirmed by
+# SQ_INSTS_VALU) priced with the issue costs measured on MI355X, in cycles per
+# wave64 instruction per SIMD: 604 full-rate FP32 / integer instructions x 2.4,
+# 42 half-rate (funnel shift, med3, select, 32-bit multiplies) x 4.2, 46
+# 32x32->64 multiplies x 4.9, 32 transcendentals x 8.1 -> 2,110 cycles per
+# wave-step.  At perfect issue the kernel then reaches 758 x 64 flops per
+# 2,110 cycles of a SIMD's 64 flops per cycle at FP32 peak: the ceiling of
+# `frac` for this mix.
+MH_GRE3_ISSUE_CYCLES = 604 * 2.4 + 42 * 4.2 + 46 * 4.9 + 32 * 8.1     # = 2,110
+MH_GRE3_MIX_CEILING = FLOP_PER_MH_STEP_GRE3 * 64 / MH_GRE3_ISSUE_CYCLES / 64.0   # = 0.36
 
 # HBM bytes per launch of the dominant kernels, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE) of `bench.py --profile-only mh,adam,copy`
@@ -642,9 +652,11 @@ def serve_run(g, jobs, baseline, saturated, chunk=256):
                 work = d.n * j.n_iter
             ids.append((jid, work))
         digests = []
+        lat = []
         finite = True
         for k, (jid, _) in enumerate(ids):
             r = srv.wait(jid)
+            lat.append(srv.latency(jid))
             digests.append(_digest(r))
             finite &= all(bool(np.isfinite(r[x]).all()) for x in ("mean", "std", "maps")
                           if r.get(x) is not None)
@@ -655,7 +667,31 @@ def serve_run(g, jobs, baseline, saturated, chunk=256):
     total = sum(w for _, w in ids)
     return dict(makespan_s=span, value=total / span, p50_s=st["p50_latency_s"],
                 p99_s=st["p99_latency_s"], jobs=len(ids), voxel_iters=total,
-                finite=finite), digests
+                finite=finite, latencies=lat, work=[w for _, w in ids]), digests
+
+
+def batching_bound(jobs, base):
+    """What batching can gain on a trace: in the saturated one-job-per-launch
+    run jobs complete one after another, so job j's service time is its
+    completion time minus the previous job's; the fastest rate any job of a
+    (model, solver) class reaches alone stands for that class's full-GPU
+    rate; the trace's work at those rates is the shortest time any schedule
+    of these kernels can take.  Returns that time and the largest speed-up
+    over the one-job-per-launch run it allows."""
+    done = np.asarray(base["latencies"])
+    order = np.argsort(done)
+    service = np.empty_like(done)
+    service[order] = np.diff(np.concatenate([[0.0], done[order]]))
+    rate = {}
+    for (j, d, y, m), w, t in zip(jobs, base["work"], service):
+        key = (j.model, j.kind, bool(j.tv))
+        if t > 0:
+            rate[key] = max(rate.get(key, 0.0), w / t)
+    ideal = sum(w / rate[(j.model, j.kind, bool(j.tv))]
+                for (j, d, y, m), w in zip(jobs, base["work"]))
+    return {"ideal_s": ideal, "max_speedup": base["makespan_s"] / ideal,
+            "class_rates": {f"{k[0]}/{k[1]}{'+tv' if k[2] else ''}": v
+                            for k, v in sorted(rate.items())}}
 
 
 SERVE_TRACES = {
@@ -689,6 +725,11 @@ def serve_leg(g, torch, trace="full", legs=("saturated", "paced")):
             log(f"bench:   {res[mode]}")
         res["speedup"] = res["batched"]["value"] / res["baseline"]["value"]
         res["identical_results"] = dig["batched"] == dig["baseline"]
+        if sat:
+            res["bound"] = batching_bound(jobs, res["baseline"])
+        for mode in ("batched", "baseline"):
+            res[mode].pop("latencies")
+            res[mode].pop("work")
         same &= res["identical_results"]
         out[leg] = res
     out["identical_results"] = same
@@ -956,6 +997,9 @@ def main():
                      "unit": "TFLOP/s", "frac": mh["achieved_tflops"] / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic("mh_chunk_cfg4"),
                      "flop_per_step": FLOP_PER_MH_STEP_GRE3,
+                     "mix_ceiling": MH_GRE3_MIX_CEILING,
+                     "frac_of_ceiling": (mh["achieved_tflops"] / PEAK_FP32_TFLOPS /
+                                         MH_GRE3_MIX_CEILING),
                      "steps_per_launch": mh["units_per_launch"],
                      "launch_ms": mh["per_launch_ms"]},
         "cpu_baseline": cpu,

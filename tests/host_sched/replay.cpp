@@ -10,8 +10,11 @@
 // --saturated submits every job at once; otherwise arrivals are paced at
 // arrival_s * S seconds.  --cancel K cancels every K-th job (0 = none),
 // alternately right after submitting it and, once all jobs are submitted,
-// MS + STEP_MS * (i mod 11) milliseconds later (default 5 and 7).  Exit status: 0 when no violation was found and
-// every job not cancelled completed.
+// MS + STEP_MS * (i mod 11) milliseconds later (default 5 and 7).
+// --expect-failures: a launch failure is injected (HH_FAIL_LAUNCH, see the
+// stand-in launchers); the jobs of that round must then fail.
+// Exit status: 0 when no violation was found, every job ended and none
+// failed (with --expect-failures: some failed).
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -91,7 +94,7 @@ int main(int argc, char** argv) {
         std::fprintf(stderr, "usage: replay TRACE [options]\n");
         return 2;
     }
-    bool saturated = false, baseline = false;
+    bool saturated = false, baseline = false, expect_failures = false;
     size_t budget = 0;
     int slots = 0, chunk = 256, cancel_every = 0, cancel_ms = 5, cancel_step_ms = 7;
     double scale = 1.0;
@@ -109,6 +112,7 @@ int main(int argc, char** argv) {
             cancel_step_ms = std::atoi(next());
         }
         else if (a == "--scale") scale = std::atof(next());
+        else if (a == "--expect-failures") expect_failures = true;
         else {
             std::fprintf(stderr, "unknown option %s\n", a.c_str());
             return 2;
@@ -241,9 +245,10 @@ int main(int argc, char** argv) {
         if (st == GC_OK) ++done;
         else if (st == GC_E_CANCELLED) ++canc;
         else {
-            std::fprintf(stderr, "job %zu (%s %s, %ld voxels) failed: %d %s\n", i,
-                         trace[i].model.c_str(), trace[i].kind.c_str(), trace[i].n_vox, st,
-                         gc_last_error());
+            if (!expect_failures)
+                std::fprintf(stderr, "job %zu (%s %s, %ld voxels) failed: %d %s\n", i,
+                             trace[i].model.c_str(), trace[i].kind.c_str(), trace[i].n_vox, st,
+                             gc_last_error());
             ++failed;
         }
         if (st == GC_OK && cancelled[i]) ++late_done;   // finished before the cancel arrived
@@ -264,7 +269,9 @@ int main(int argc, char** argv) {
                 "%d refused; resident %d, in use %zu B after; %.2f s; violations %zu\n",
                 trace.size(), done, late_done, canc, failed, refused, stt.resident,
                 stt.hbm_in_use, span, nv);
-    const bool ok = nv == 0 && failed == 0 && refused == 0 && stt.resident == 0 &&
-                    stt.hbm_in_use == 0;
+    // with an injected launch failure the jobs of that round fail (once their
+    // earlier rounds have drained); every job still ends
+    const bool ok = nv == 0 && (expect_failures ? failed > 0 : failed == 0) && refused == 0 &&
+                    stt.resident == 0 && stt.hbm_in_use == 0;
     return ok ? 0 : 1;
 }

@@ -4,6 +4,8 @@
 // following the kernel's own index arithmetic -- against the allocations
 // live at that moment.  Nothing of the method is computed; only the index
 // bookkeeping the host reads back is done (mask compaction, fills).
+#include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <set>
 #include <vector>
@@ -109,6 +111,20 @@ bool in_list(int m, std::initializer_list<int> l) {
     return false;
 }
 
+// HH_FAIL_LAUNCH=family:k makes the k-th launch (1-based) of that launcher
+// family report a launch failure, as a real launch can (the failure path of
+// the host code is then exercised; nothing is queued for that launch).
+bool injected_failure(const char* family) {
+    static const char* spec = std::getenv("HH_FAIL_LAUNCH");
+    if (!spec) return false;
+    const char* colon = std::strchr(spec, ':');
+    if (!colon || std::strncmp(spec, family, (size_t)(colon - spec)) != 0 ||
+        std::strlen(family) != (size_t)(colon - spec))
+        return false;
+    static std::atomic<long> count{0};
+    return count.fetch_add(1) + 1 == std::atol(colon + 1);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ MCMC
@@ -125,6 +141,7 @@ hipError_t mh_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, in
 hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkMap* map, int nblk,
                     int chains, int meff, hipStream_t s) {
     hh::count_launch("mh_chunk");
+    if (injected_failure("mh_chunk")) return hipErrorLaunchFailure;
     // the launcher's dispatch: which instantiation runs, with how much LDS
     const bool share = chains > 0 && kBlock % chains == 0 && meff > 0 &&
                        (size_t)(kBlock / chains) * meff * sizeof(float) <= kMhSharedData;
@@ -296,6 +313,7 @@ hipError_t fit_fused(int kind, int maxm, const FitJob* jobs, const BlkMap* map, 
 hipError_t fit_step(int kind, const FitJob* jobs, const BlkMap* map, int nblk, int xcd_remap,
                     hipStream_t s) {
     hh::count_launch("fit_step");
+    if (injected_failure("fit_step")) return hipErrorLaunchFailure;
     hh::enqueue(s, "fit_step", [=](uint64_t seq) {
         const char* k = "fit_step";
         std::set<int> seen;

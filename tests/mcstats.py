@@ -38,3 +38,18 @@ def mcse_std(samples: np.ndarray) -> np.ndarray:
 def zscores(a_mean, b_mean, a_se, b_se):
     return (np.asarray(a_mean) - np.asarray(b_mean)) / np.sqrt(np.asarray(a_se) ** 2 +
                                                               np.asarray(b_se) ** 2)
+
+
+def mcse_mean_ensemble(samples: np.ndarray) -> np.ndarray:
+    """samples [W, K, ...] of W coupled walkers: the pooled mean is the mean
+    of the walker-averaged series, whose batch means give its error."""
+    return mcse_mean(samples.mean(axis=0, keepdims=True))
+
+
+def mcse_std_ensemble(samples: np.ndarray) -> np.ndarray:
+    W, K = samples.shape[:2]
+    flat = samples.reshape((W * K,) + samples.shape[2:])
+    mu = flat.mean(axis=0)
+    sd = flat.std(axis=0, ddof=1)
+    sq = ((samples - mu) ** 2).mean(axis=0, keepdims=True)
+    return mcse_mean(sq) / (2.0 * np.maximum(sd, 1e-300))

@@ -110,32 +110,58 @@ def test_adam_cfg0_matches_oracle(orc):
     assert out["final_loss"] == pytest.approx(ref["loss"][-1], rel=1e-4)
 
 
-@pytest.mark.parametrize("opt", ["adam", "sgdm", "rmsprop"])
+def _u_err(maps, ref_maps, d):
+    """|u - u_ref| over the masked voxels, u = (theta - lb) / (ub - lb)."""
+    sel = d.mask.astype(bool)
+    a = maps[:, sel] if maps.ndim == 4 else maps
+    b = ref_maps[:, sel] if ref_maps.ndim == 4 else ref_maps
+    return np.abs(a - b) / (d.ub - d.lb)[:, None]
+
+
+def _within_fp32_rounding(err, emu_err, tag, factor=5.0, floor=1e-6):
+    """The GPU may depart from the FP64 oracle by what FP32 rounding alone
+    produces: an FP32 re-run of the same algorithm (tests/fp32_emulation.py)
+    gives that spread; the GPU's median, 99th percentile and maximum must stay
+    within `factor` times the re-run's (plus a floor at the FP32 resolution of
+    the maps).  Where the iteration amplifies rounding (TV subgradient signs of
+    nearly equal neighbours, RMS-normalised steps), both spreads are large
+    together; where it does not, both stay at the rounding level."""
+    stats = [("median", np.median), ("p99", lambda x: np.quantile(x, 0.99)), ("max", np.max)]
+    for name, f in stats:
+        a, b = float(f(err)), float(f(emu_err))
+        say(f"  {tag} {name}: gpu {a:.2e}  fp32 re-run {b:.2e}")
+        assert a <= factor * b + floor, (tag, name, a, b)
+
+
+@pytest.mark.parametrize("opt,rate", [("adam", None), ("sgdm", 0.005), ("sgdm", 0.001),
+                                      ("rmsprop", None)])
 @pytest.mark.parametrize("model", ["monoexp_r2s", "gre3", "dwi2", "linear3"])
-def test_fits_match_oracle(orc, model, opt):
+def test_fits_match_oracle(orc, model, opt, rate):
+    import fp32_emulation as em
     shape = (3, 7, 9)
     d = synth.make_draw(model, shape, 12, 0.01, acq=ACQS[model])
     yg = _fit_inputs(orc, d)
     m = G().Model.from_acq(model, d.acq)
     kw = dict(n_iter=120, optimizer=opt, lr=0.01)
     if opt != "adam":
-        # plain (momentum / RMS-scaled) gradient steps: a step size that moves
-        # u by at most ~0.5 % at the start, and fewer iterations, so the
-        # comparison stays in the smooth regime before limit cycles set in
+        # plain (momentum / RMS-scaled) gradient steps over 40 iterations; the
+        # SGDM rate is given as the fraction of u its first step may move
         mid = np.broadcast_to((0.5 * (d.lb + d.ub))[:, None], (d.n_params, d.n))
         ycomp = synth.gather(yg, d.mask)
         _, gth = orc.loss_grad(model, d.acq, mid, ycomp, p=2,
                                scale=1.0 / (d.n * m.n_meas_eff))
         gmax = np.abs((d.ub - d.lb)[:, None] * gth).max()
-        kw.update(n_iter=40, lr=0.001 / gmax if opt == "sgdm" else 0.002)
+        kw.update(n_iter=40, lr=rate / gmax if opt == "sgdm" else 0.002)
     out = G().gc_fit_askadam(m, yg, d.mask, d.lb, d.ub, **kw)
     ref = orc.askadam(model, d.acq, d.mask, yg, d.lb, d.ub, n_threads=8, **kw)
-    u_out = (out["maps"] - d.lb[:, None, None, None]) / (d.ub - d.lb)[:, None, None, None]
-    u_ref = (ref["maps"] - d.lb[:, None, None, None]) / (d.ub - d.lb)[:, None, None, None]
-    err = np.abs(u_out - u_ref)
-    say(model, opt, "max |du|", err.max(), "median", np.median(err))
-    assert np.median(err) < 1e-5
-    assert err.max() < 1e-3
+    emu, _ = em.askadam(model, d.acq, d.mask, yg, d.lb, d.ub, **kw)
+    err = _u_err(out["maps"], ref["maps"], d)
+    say(model, opt, rate, "max |du|", err.max(), "median", np.median(err))
+    if opt == "adam":
+        # the fitted-map bound: 1e-4 of the parameter range everywhere
+        assert err.max() <= 1e-4
+    else:
+        _within_fp32_rounding(err, _u_err(emu, ref["maps"], d), f"{model} {opt}")
 
 
 def test_fused_and_step_paths_agree():
@@ -151,24 +177,42 @@ def test_fused_and_step_paths_agree():
     assert a["final_loss"] == pytest.approx(b["final_loss"], rel=1e-5)
 
 
-def test_adam_tv_matches_oracle(orc):
-    d = synth.make_draw("dwi2", (6, 8, 10), 2, 0.02, acq=_dwi_acq(per=8), block=4)
+def _adam_tv_against_oracle(orc, d, n_iter, tag):
+    import fp32_emulation as em
     yg = _fit_inputs(orc, d)
     m = G().Model.from_acq("dwi2", d.acq)
-    kw = dict(n_iter=100, lam=1e-3, tv_params=(0, 1, 2), tv_dim=3)
+    kw = dict(n_iter=n_iter, lam=1e-3, tv_params=(0, 1, 2), tv_dim=3)
     out = G().gc_fit_askadam(m, yg, d.mask, d.lb, d.ub, loss_history=True, **kw)
     ref = orc.askadam("dwi2", d.acq, d.mask, yg, d.lb, d.ub, lam=1e-3, tv_mask=0b111, tv_dim=3,
-                      n_iter=100, n_threads=8)
-    u_out = (out["maps"] - d.lb[:, None, None, None]) / (d.ub - d.lb)[:, None, None, None]
-    u_ref = (ref["maps"] - d.lb[:, None, None, None]) / (d.ub - d.lb)[:, None, None, None]
-    err = np.abs(u_out - u_ref)
-    say("adam+tv max |du|", err.max(), "median", np.median(err), "p99",
-        np.quantile(err, 0.99))
-    np.testing.assert_allclose(out["loss"], ref["loss"], rtol=1e-4)
-    # the TV subgradient sign(u_b - u_a) of nearly equal neighbours can flip
-    # between FP32 and FP64 and the flips propagate through the coupled
-    # iterates, so the maps agree to 1e-4 of the range in the median only
-    assert np.median(err) < 1e-4 and np.quantile(err, 0.99) < 5e-3 and err.max() < 2e-2
+                      n_iter=n_iter, n_threads=16)
+    emu, hist = em.askadam("dwi2", d.acq, d.mask, yg, d.lb, d.ub, n_iter=n_iter, lam=1e-3,
+                           tv_mask=0b111, tv_dim=3)
+    err = _u_err(out["maps"], ref["maps"], d)
+    emu_err = _u_err(emu, ref["maps"], d)
+    _within_fp32_rounding(err, emu_err, tag)
+    lrel = np.abs(np.asarray(out["loss"]) / ref["loss"] - 1)
+    erel = np.abs(hist / ref["loss"] - 1)
+    say(f"  {tag} loss rel: gpu {lrel.max():.2e}  fp32 re-run {erel.max():.2e}")
+    assert lrel.max() <= 5 * erel.max() + 1e-6
+
+
+def test_adam_tv_matches_oracle(orc):
+    """TV fits: the subgradient sign(u_b - u_a) of nearly equal neighbours
+    flips with the rounding of the arithmetic and Adam's normalised step turns
+    each flip into a full-size move, so FP32 and FP64 trajectories part by
+    up to ~1e-2 of the range in a few voxels; the bound is what an FP32 re-run
+    of the algorithm itself shows."""
+    d = synth.make_draw("dwi2", (6, 8, 10), 2, 0.02, acq=_dwi_acq(per=8), block=4)
+    _adam_tv_against_oracle(orc, d, 100, "adam+tv 6x8x10")
+
+
+@pytest.mark.timeout(900)
+def test_adam_tv_diffusion_workload_32cubed_whole_volume(orc):
+    """The 64^3 diffusion workload's recipe (piecewise-constant maps on 8^3
+    blocks, 96 measurements, sigma 0.02, Adam 500 iterations, TV 1e-3 on f,
+    Da, De) on a 32^3 volume, every voxel against the oracle."""
+    d = synth.cfg2(shape=(32, 32, 32))
+    _adam_tv_against_oracle(orc, d, synth.CFG2_ADAM["n_iter"], "adam+tv 32^3 x 500")
 
 
 def test_tv_gradient_in_fit_matches_oracle(orc):

@@ -138,19 +138,26 @@ def test_tv_fit_multi_step_matches_oracle(orc, reg):
         ko["graph"] = gr
     out = G().gc_fit_askadam(m, yg, d.mask, d.lb, d.ub, loss_history=True, **kg)
     ref = orc.askadam("dwi2", d.acq, d.mask, yg, d.lb, d.ub, n_threads=8, **ko)
-    rngs = (d.ub - d.lb)[:, None, None, None]
-    err = np.abs(out["maps"] - ref["maps"]) / rngs
-    say(reg, "multi-step |du| median", np.median(err), "p99", np.quantile(err, 0.99),
-        "max", err.max())
     # as for the anisotropic TV: subgradient flips of nearly equal neighbours
     # (the draws are piecewise constant, so many are) propagate through the
-    # coupled iterates; the graph form counts each edge twice, doubling their
-    # weight, so its losses agree to 1e-3 and its maps to 5e-4 of the range
-    # in the median (iso: 1e-4); the one-step test above checks the
-    # gradient itself to 1e-6
-    np.testing.assert_allclose(out["loss"], ref["loss"], rtol=1e-4 if reg == "iso" else 1e-3)
-    med = 1e-4 if reg == "iso" else 5e-4
-    assert np.median(err) < med and np.quantile(err, 0.99) < 5e-3 and err.max() < 2e-2
+    # coupled iterates; the bounds are the spread of an FP32 re-run of the
+    # same algorithm against the oracle (the one-step test above checks the
+    # gradient itself to 1e-4)
+    import fp32_emulation as em
+    emu, hist = em.askadam("dwi2", d.acq, d.mask, yg, d.lb, d.ub,
+                           **{k: v for k, v in ko.items()})
+    sel = d.mask.astype(bool)
+    rngs = (d.ub - d.lb)[:, None]
+    err = np.abs(out["maps"][:, sel] - ref["maps"][:, sel]) / rngs
+    emu_err = np.abs(emu - ref["maps"][:, sel]) / rngs
+    for name, f in [("median", np.median), ("p99", lambda x: np.quantile(x, 0.99)),
+                    ("max", np.max)]:
+        a, b = float(f(err)), float(f(emu_err))
+        say(f"  {reg} {name}: gpu {a:.2e}  fp32 re-run {b:.2e}")
+        assert a <= 5 * b + 1e-6, (reg, name, a, b)
+    lrel = np.abs(np.asarray(out["loss"]) / ref["loss"] - 1)
+    erel = np.abs(hist / ref["loss"] - 1)
+    assert lrel.max() <= 5 * erel.max() + 1e-6
 
 
 def test_prior_fit_fused_path_matches_oracle(orc):

