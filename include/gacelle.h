@@ -283,6 +283,27 @@ int gc_mcmc(const gc_model *model, const gc_volume *data, const uint8_t *mask,
             const gc_mcmc_hyper *hyper, double *out_mean, double *out_std,
             float *out_samples, int32_t *out_accept, const gc_exec *exec);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): gc_mcmc with the
+ * same arguments and results, but every piece of device scratch (compacted
+ * data, index maps, chain state, moments, descriptors, the model's
+ * acquisition tables) comes from one fixed device array per GPU of
+ * gc_noalloc_scratch_bytes() bytes (128 MiB), held until the process ends;
+ * nothing is allocated or freed.  All bulk arguments must be device memory
+ * (exec->mem_kind = GC_MEM_DEVICE) and no sample sink may be given
+ * (GC_E_INVAL otherwise).  A problem whose scratch does not fit is refused
+ * with GC_E_NOMEM (gc_last_error says by how much); work queued before the
+ * refusal has finished when the call returns.  Calls on one GPU share its
+ * array: the library runs them one at a time, and each returns only after
+ * its work on the array has finished, so results never depend on an earlier
+ * call's leftovers.  Calls from other processes use their own arrays. */
+int gc_mcmc_noalloc(const gc_model *model, const gc_volume *data, const uint8_t *mask,
+                    const gc_bounds *bounds, int n_chains, int n_iter, int burnin, int thin,
+                    const gc_mcmc_hyper *hyper, double *out_mean, double *out_std,
+                    float *out_samples, int32_t *out_accept, const gc_exec *exec);
+/* Size in bytes of gc_mcmc_noalloc's per-GPU scratch array. */
+size_t gc_noalloc_scratch_bytes(void);
+
 /* ------------------------------------------------------------------------
  * Forward / adjoint entry points (compacted voxels, exec memory), the
  * building blocks of automatic differentiation (paper §2.2.1 relies on

@@ -162,6 +162,10 @@ _sig = {
     "gc_burnin_from_ratio": ([c_double, c_int], c_int),
     "gc_mcmc": ([P, ctypes.POINTER(gc_volume), P, ctypes.POINTER(gc_bounds), c_int, c_int, c_int,
                  c_int, ctypes.POINTER(gc_mcmc_hyper), P, P, P, P, ctypes.POINTER(gc_exec)], c_int),
+    "gc_mcmc_noalloc": ([P, ctypes.POINTER(gc_volume), P, ctypes.POINTER(gc_bounds), c_int, c_int,
+                         c_int, c_int, ctypes.POINTER(gc_mcmc_hyper), P, P, P, P,
+                         ctypes.POINTER(gc_exec)], c_int),
+    "gc_noalloc_scratch_bytes": ([], c_size_t),
     "gc_model_forward": ([P, P, c_int64, P, ctypes.POINTER(gc_exec)], c_int),
     "gc_model_vjp": ([P, P, c_int64, P, P, ctypes.POINTER(gc_exec)], c_int),
     "gc_loss_vjp": ([P, P, P, P, c_int64, c_int, c_double, P, P, ctypes.POINTER(gc_exec)], c_int),
@@ -337,6 +341,9 @@ def gc_version() -> str:
     return _L.gc_version().decode()
 
 
+def gc_noalloc_scratch_bytes() -> int:
+    return int(_L.gc_noalloc_scratch_bytes())
+
 
 def gc_burnin_from_ratio(ratio: float, n_iter: int) -> int:
     return int(_L.gc_burnin_from_ratio(ratio, n_iter))
@@ -422,7 +429,8 @@ def gc_mcmc(model: Model, y, mask, lb, ub, n_chains, n_iter, burnin, thin, *, si
             step=None, seed=0, x0=None, x0_map=None, x0_mode="midpoint", weights=None,
             precision="fp32", sampler="mh", n_walkers=50, stretch=2.0, chunk_iters=0,
             samples=False, accept=True, final_state=False, out_mean=None, out_std=None,
-            t_start=0, init_state=None, init_logl=None, sample_sink=None, sink_bytes=0):
+            t_start=0, init_state=None, init_logl=None, sample_sink=None, sink_bytes=0,
+            noalloc=False):
     """Returns dict(mean, std [P, nz, ny, nx] float64, accept [C, nz, ny, nx],
     samples [C, K, P, n_masked] float32 or None, final_state [P, C, n], final_logl [C, n]).
 
@@ -433,7 +441,12 @@ def gc_mcmc(model: Model, y, mask, lb, ub, n_chains, n_iter, burnin, thin, *, si
     chains run, in deliveries of at most sink_bytes (0 = 256 MiB): samples is a
     float32 view [C, k, P, n_masked] of host memory valid only during the call
     (copy what you keep); returning False stops the run (GcError
-    GC_E_CANCELLED).  Not with samples=True."""
+    GC_E_CANCELLED).  Not with samples=True.
+
+    noalloc: call gc_mcmc_noalloc, which allocates no device memory (all its
+    scratch lives in a fixed per-GPU array of gc_noalloc_scratch_bytes());
+    every bulk argument must then be a torch tensor on the GPU, outputs
+    included (out_mean and out_std, or none given)."""
     a = _Args()
     nx, ny, nz = _shape3(y, model)
     vol = gc_volume(nx, ny, nz, a.ptr(y, np.float32))
@@ -483,8 +496,9 @@ def gc_mcmc(model: Model, y, mask, lb, ub, n_chains, n_iter, burnin, thin, *, si
     ex_ptrs = (a.out(mean, np.float64), a.out(std, np.float64), a.out(smp, np.float32),
                a.out(acc, np.int32))
     ex = a.exec()
-    _check(_L.gc_mcmc(model.handle, ctypes.byref(vol), mp, ctypes.byref(b), n_chains, n_iter,
-                      burnin, thin, ctypes.byref(h), *ex_ptrs, ctypes.byref(ex)))
+    fn = _L.gc_mcmc_noalloc if noalloc else _L.gc_mcmc
+    _check(fn(model.handle, ctypes.byref(vol), mp, ctypes.byref(b), n_chains, n_iter,
+              burnin, thin, ctypes.byref(h), *ex_ptrs, ctypes.byref(ex)))
     return dict(mean=mean, std=std, accept=acc, samples=smp, final_state=fs, final_logl=fl)
 
 

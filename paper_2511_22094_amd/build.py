@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libgacelle.so")
-SOURCES = ["gc_pack.hip", "gc_mh.hip", "gc_ens.hip", "gc_fit.hip", "gc_sense.hip", "gc_capi.cpp", "gc_variants.cpp",
+SOURCES = ["gc_pack.hip", "gc_mh.hip", "gc_ens.hip", "gc_fit.hip", "gc_sense.hip", "gc_capi.cpp", "gc_variants.cpp", "gc_noalloc.cpp",
            "gc_timing.cpp", "gc_server.cpp"]
 ARCH = os.environ.get("GACELLE_ARCH", "gfx950")
 
