@@ -186,6 +186,24 @@ typedef struct {
     uint32_t prior_mask;   /* bit p set: prior on parameter p */
     const float *prior_mu;    /* [P][nz][ny][nx] prior means (exec memory) */
     const float *prior_sigma; /* [P][nz][ny][nx] prior SDs > 0 (exec memory) */
+    /* Checkpoint / resume.  The optimiser state after iteration t is the
+     * normalised iterate u_t with the first and second moments m_t, v_t
+     * (SGDM keeps its velocity in m, RMSProp its squared-gradient average in
+     * v; the unused plane is 0), laid out [3][P][n_masked] FP32 (u, m, v;
+     * voxels in mask order, n_masked = gc_count_mask), exec memory.
+     * final_state (or NULL) receives the state after the last iteration run.
+     * With t_start > 0 the call runs iterations t_start + 1 .. n_iter from
+     * init_state, the final_state of a call that ran t_start iterations
+     * (the bounds' start values are then ignored): with the same data and
+     * settings the iterates, losses and stopping decisions are those of one
+     * uninterrupted call.  A convergence window (conv_value > 0) looks back
+     * over earlier iterations: on resume loss_history is then required and
+     * must hold the first t_start losses, which the call keeps and extends.
+     * iters_run in the report counts from iteration 1.  Not for server
+     * jobs. */
+    int t_start;              /* iterations already run (0 = fresh start) */
+    const float *init_state;  /* [3][P][n_masked] state after t_start (t_start > 0) */
+    float *final_state;       /* [3][P][n_masked] state after the last iteration, or NULL */
 } gc_adam_hyper;
 
 typedef struct {
@@ -412,7 +430,17 @@ int gc_philox_uniform_normal(uint64_t seed, const uint32_t *ctr, int64_t n, int 
  * launch of a family within one call (k = 1: every launch), which bounds
  * the cost of the two event records per timed launch for families launched
  * once per iteration.  The count returned by gc_timing_get is that of the
- * timed launches.
+ * timed launches.  Server rounds are read out when the round completes.
+ *
+ * Trace: with the environment variable GACELLE_TRACE set to a file name when
+ * the library is loaded, timing is on (every launch) and each timed launch
+ * is also recorded -- family, device, stream, start and duration -- and
+ * written at process exit to that file as Chrome trace-event JSON
+ * ({"traceEvents": [{"name", "ph": "X", "pid": device, "tid": stream,
+ * "ts", "dur"} ...]}, microseconds).  Start times count from a reference
+ * event recorded once per device, after a device synchronisation, when its
+ * first traced launch begins.  The two event records per launch cost a few
+ * microseconds each: tracing is a profiling mode, not for timing runs.
  * ------------------------------------------------------------------------ */
 int gc_timing_enable(int on);
 /* Total event time (ms) and launch count of a family since the last reset. */

@@ -79,7 +79,8 @@ class gc_adam_hyper(ctypes.Structure):
                 ("loss_history", c_void_p), ("tv_kind", c_int), ("graph_n", c_int64),
                 ("graph_nnz", c_int64), ("graph_rowptr", c_void_p), ("graph_col", c_void_p),
                 ("prior_lambda", c_double), ("prior_mask", c_uint32), ("prior_mu", c_void_p),
-                ("prior_sigma", c_void_p)]
+                ("prior_sigma", c_void_p), ("t_start", c_int), ("init_state", c_void_p),
+                ("final_state", c_void_p)]
 
 
 TV_KINDS = {"aniso": 0, "iso": 1, "graph": 2}
@@ -386,12 +387,20 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
                    rho=0.9, n_iter=200, loss=2, lam=0.0, tv_params: Sequence[int] = (),
                    tv_dim=3, tol=0.0, conv_value=0.0, conv_window=20, loss_history=False,
                    out=None, tv_kind="aniso", graph=None, prior_lam=0.0,
-                   prior_params: Sequence[int] = (), prior_mu=None, prior_sigma=None):
-    """Returns dict(maps [P, nz, ny, nx] float32, iters_run, final_loss, stop_reason[, loss]).
+                   prior_params: Sequence[int] = (), prior_mu=None, prior_sigma=None,
+                   t_start=0, init_state=None, final_state=False):
+    """Returns dict(maps [P, nz, ny, nx] float32, iters_run, final_loss, stop_reason[, loss]
+    [, final_state]).
 
     tv_kind "aniso" | "iso" | "graph" (graph = (rowptr [n+1] int64, col int32) over the
     masked voxels in grid order); prior_mu / prior_sigma [P, nz, ny, nx] for the prior
-    term on prior_params."""
+    term on prior_params.
+
+    Checkpoint / resume: final_state=True returns the optimiser state
+    [3, P, n_masked] float32 (u, m, v) after the last iteration; t_start > 0
+    with init_state = that state of a call that ran t_start iterations runs
+    iterations t_start + 1 .. n_iter.  loss_history may then be the earlier
+    call's losses (their first t_start entries seed the convergence window)."""
     a = _Args()
     nx, ny, nz = _shape3(y, model)
     vol = gc_volume(nx, ny, nz, a.ptr(y, np.float32))
@@ -409,11 +418,29 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
     h.tol, h.conv_value, h.conv_window = tol, conv_value, conv_window
     _set_regularisers(h, a, model, tv_kind, graph, prior_lam, prior_params, prior_mu,
                       prior_sigma)
+    prev = None
+    if loss_history is not None and not isinstance(loss_history, bool):
+        prev = np.asarray(loss_history, np.float64)[: int(t_start)]
+        loss_history = True
     hist = np.zeros(max(n_iter, 1)) if loss_history else None
+    if prev is not None:
+        hist[: prev.size] = prev
     h.loss_history = None if hist is None else hist.ctypes.data
     maps = out if out is not None else _empty_like_kind(a, (model.n_params, nz, ny, nx),
                                                        np.float32, y)
     mo = a.out(maps, np.float32)
+    h.t_start = int(t_start)
+    h.init_state = a.ptr(init_state, np.float32)
+    fs = None
+    if final_state:
+        if mask is None:
+            n = nx * ny * nz
+        elif _is_torch(mask):
+            n = int(mask.sum().item())
+        else:
+            n = int(np.count_nonzero(mask))
+        fs = _empty_like_kind(a, (3, model.n_params, n), np.float32, y)
+    h.final_state = a.out(fs, np.float32)
     rep = gc_fit_report()
     ex = a.exec()
     _check(_L.gc_fit_askadam(model.handle, ctypes.byref(vol), mp, ctypes.byref(b),
@@ -422,6 +449,8 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
              stop_reason=rep.stop_reason)
     if hist is not None:
         r["loss"] = hist[: rep.iters_run]
+    if fs is not None:
+        r["final_state"] = fs
     return r
 
 

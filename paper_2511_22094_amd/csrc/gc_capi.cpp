@@ -498,6 +498,13 @@ int validate_adam(const gc_model* m, const gc_adam_hyper* h) {
                GC_E_INVAL, "the prior needs prior_mu and prior_sigma");
     GC_REQUIRE(!(h->conv_value > 0) || h->conv_window > 1, GC_E_INVAL,
                "conv_window must be > 1");
+    GC_REQUIRE(h->t_start >= 0 && h->t_start < h->n_iter, GC_E_INVAL,
+               "t_start must be in [0, n_iter)");
+    GC_REQUIRE(h->t_start == 0 || h->init_state, GC_E_INVAL,
+               "resume (t_start > 0) needs init_state");
+    GC_REQUIRE(h->t_start == 0 || !(h->conv_value > 0) || h->loss_history, GC_E_INVAL,
+               "resume with a convergence window needs loss_history holding the first "
+               "t_start losses");
     return GC_OK;
 }
 
@@ -655,6 +662,27 @@ int gc_burnin_from_ratio(double ratio, int n_iter) {
 }
 
 // ------------------------------------------------------------------ askadam
+}  // extern "C"
+
+namespace gc {
+// The optimiser state [3][P][n] (u, m, v) of a fit: in = caller's state into
+// the iterate buffer u and the moments m, v; out = the reverse.  The caller's
+// array is exec memory (host or device), the copies are ordered on s.
+static hipError_t copy_state(const void* st, float* u, float* m, float* v, size_t np, bool in,
+                             hipStream_t s) {
+    float* bufs[3] = {u, m, v};
+    for (int k = 0; k < 3; ++k) {
+        float* ext = (float*)st + (size_t)k * np;
+        hipError_t e = in ? hipMemcpyAsync(bufs[k], ext, np * sizeof(float), hipMemcpyDefault, s)
+                          : hipMemcpyAsync(ext, bufs[k], np * sizeof(float), hipMemcpyDefault, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+}  // namespace gc
+
+extern "C" {
+
 int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* mask,
                    const gc_bounds* bounds, const gc_adam_hyper* hyper, float* out_maps,
                    gc_fit_report* report, const gc_exec* exec) {
@@ -677,6 +705,7 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
     const int P = model->P;
     const int64_t n = pk.n, G = pk.G;
     const int T = hyper->n_iter;
+    const int t_start = hyper->t_start;
     FitJob J;
     if ((rc = fill_fit_job(model, bounds, hyper, n, acq, &J))) return rc;
     J.y = pk.y;
@@ -721,14 +750,20 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
         if (!tv && !stopping && !history) {
             // fused path: the whole loop in registers, chunks of <= 1000 iterations
             const int chunk = 1000;
-            const int nck = (T + chunk - 1) / chunk;
+            const int nck = (T - t_start + chunk - 1) / chunk;
             jobs.assign(nck, J);
             float* lossv = nullptr;
             GC_TRY_HIP(sc.alloc_n(&lossv, (size_t)n));
+            // bias-correction powers after t_start iterations, multiplied in
+            // the order the kernel multiplies them
             double b1 = 1.0, b2 = 1.0;
+            for (int t = 1; t <= t_start; ++t) {
+                b1 *= hyper->beta1;
+                b2 *= hyper->beta2;
+            }
             for (int c = 0; c < nck; ++c) {
-                jobs[c].t0 = c * chunk + 1;
-                jobs[c].t1 = std::min(T, (c + 1) * chunk);
+                jobs[c].t0 = t_start + c * chunk + 1;
+                jobs[c].t1 = std::min(T, t_start + (c + 1) * chunk);
                 jobs[c].b1pow = b1;
                 jobs[c].b2pow = b2;
                 for (int t = jobs[c].t0; t <= jobs[c].t1; ++t) {
@@ -740,7 +775,8 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
             }
             GC_TRY_HIP(sc.alloc_n(&djob, (size_t)nck));
             GC_TRY_HIP(hipMemcpyAsync(djob, jobs.data(), nck * sizeof(FitJob), hipMemcpyHostToDevice, s));
-            GC_TRY_HIP(fit_init(djob, dmap, (int)nblk, s));
+            if (t_start == 0) GC_TRY_HIP(fit_init(djob, dmap, (int)nblk, s));
+            else GC_TRY_HIP(copy_state(hyper->init_state, u0, m, v, np, true, s));
             const int maxm = fit_pick_maxm(model->kind, model->M);
             LaunchTimer tm("fit_fused", s);
             for (int c = 0; c < nck; ++c) {
@@ -757,6 +793,8 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
             GC_TRY_HIP(sum_partials(lossv, n, dl, s));
             GC_TRY_HIP(hipMemcpyAsync(&final_loss, dl, sizeof(double), hipMemcpyDeviceToHost, s));
             GC_TRY_HIP(fit_theta(P, J.lb, J.rng, u0, n, theta_c, s));
+            if (hyper->final_state)
+                GC_TRY_HIP(copy_state(hyper->final_state, u0, m, v, np, false, s));
         } else {
             // step path: one launch per iteration, double-buffered iterate
             int32_t* nbr = nullptr;
@@ -794,12 +832,22 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
             }
             GC_TRY_HIP(sc.alloc_n(&djob, (size_t)T));
             GC_TRY_HIP(hipMemcpyAsync(djob, jobs.data(), T * sizeof(FitJob), hipMemcpyHostToDevice, s));
-            GC_TRY_HIP(fit_init(djob, dmap, (int)nblk, s));
+            if (t_start == 0) {
+                GC_TRY_HIP(fit_init(djob, dmap, (int)nblk, s));
+            } else {
+                // iteration t_start + 1 reads the iterate from its u_in buffer;
+                // the convergence window sees the earlier losses
+                float* uin = ((t_start + 1) % 2 == 1) ? u0 : u1;
+                GC_TRY_HIP(copy_state(hyper->init_state, uin, m, v, np, true, s));
+                if (history)
+                    GC_TRY_HIP(hipMemcpyAsync(hist, hyper->loss_history, t_start * sizeof(double),
+                                              hipMemcpyHostToDevice, s));
+            }
             const double tol = hyper->tol > 0 ? hyper->tol : -INFINITY;
             const int poll = 32;
             int hstop[2] = {0, 0};
             LaunchTimer tm("fit_step", s);
-            for (int t = 1; t <= T; ++t) {
+            for (int t = t_start + 1; t <= T; ++t) {
                 tm.begin();
                 GC_TRY_HIP(fit_step(model->kind, djob + (t - 1), dmap, (int)nblk, 1, s));
                 tm.end();
@@ -829,8 +877,10 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
                                           hipMemcpyDeviceToHost, s));
                 GC_TRY_HIP(hipStreamSynchronize(s));
             }
-            const float* ufin = (iters % 2 == 1) ? u1 : u0;
+            float* ufin = (iters % 2 == 1) ? u1 : u0;
             GC_TRY_HIP(fit_theta(P, J.lb, J.rng, ufin, n, theta_c, s));
+            if (hyper->final_state)
+                GC_TRY_HIP(copy_state(hyper->final_state, ufin, m, v, np, false, s));
         }
     }
     // scatter to the grid (0 outside the mask)

@@ -415,7 +415,7 @@ static int check_group(gc_server* S, const Group& g) {
 
 // Enqueue one round of shared launches on the compute stream.
 static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void*& rec_host,
-                        void*& rec_dev) {
+                        void*& rec_dev, std::vector<std::unique_ptr<LaunchTimer>>& timers) {
     rec_host = nullptr;
     rec_dev = nullptr;
     const int chunk = S->cfg.chunk_iters > 0 ? S->cfg.chunk_iters : 500;
@@ -560,8 +560,10 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
         Up& u = ups[ui++];
         const int nb = (int)g.map.size();
         const BlkMap* mp = (const BlkMap*)(dev + u.om);
-        LaunchTimer tm(g.kernel == 0 ? "mh_chunk" : (g.kernel == 1 ? "fit_fused" : "ens_chunk"),
-                       S->compute);
+        // timed launches are read out when the round has completed
+        timers.push_back(std::make_unique<LaunchTimer>(
+            g.kernel == 0 ? "mh_chunk" : (g.kernel == 1 ? "fit_fused" : "ens_chunk"), S->compute));
+        LaunchTimer& tm = *timers.back();
         tm.begin();
         if (g.kernel == 0) GC_TRY_HIP(mh_chunk(g.kind, g.fp64, g.maxm, (const MhJob*)(dev + u.od), mp, nb, g.walkers, g.meff, S->compute));
         else if (g.kernel == 1) GC_TRY_HIP(fit_fused(g.kind, g.maxm, (const FitJob*)(dev + u.od), mp, nb, S->compute));
@@ -573,7 +575,10 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
             Up& u = ups[ui++];
             const int nb = (int)g.map.size();
             const FitJob* dj = (const FitJob*)(dev + u.od);
+            timers.push_back(std::make_unique<LaunchTimer>("fit_step", S->compute));
+            timers.back()->begin();
             GC_TRY_HIP(fit_step(g.kind, dj, (const BlkMap*)(dev + u.om), nb, 1, S->compute));
+            timers.back()->end();
             for (size_t k = 0; k < g.fit.size(); ++k) {
                 if (!g.fit[k].record) continue;
                 Job* J = g.owners[k];
@@ -749,6 +754,7 @@ struct RoundRec {
     void* host = nullptr;      // pinned descriptor staging
     void* dev = nullptr;       // device descriptors (arena)
     std::vector<Job*> ended;   // jobs whose last work is in this round
+    std::vector<std::unique_ptr<LaunchTimer>> timers;   // the round's timed launches
 };
 
 static void scheduler(gc_server* S) {
@@ -811,7 +817,7 @@ static void scheduler(gc_server* S) {
         }
         if (!active.empty()) {
             RoundRec rec;
-            int rc = launch_round(S, round, active, rec.host, rec.dev);
+            int rc = launch_round(S, round, active, rec.host, rec.dev, rec.timers);
             if (rc != GC_OK) {
                 // work of earlier rounds may still be running on these jobs:
                 // they leave (failed) only once those rounds have drained
@@ -850,6 +856,7 @@ static void scheduler(gc_server* S) {
                                    active.empty();
             hipError_t q = must_wait ? hipEventSynchronize(r.ev) : hipEventQuery(r.ev);
             if (q == hipErrorNotReady) break;
+            for (auto& tm : r.timers) tm->flush();
             S->pinned.put(r.host);
             S->arena.free(r.dev);
             for (Job* J : r.ended)
@@ -970,6 +977,9 @@ int gc_submit(gc_server* S, const gc_job* job, uint64_t* job_id) {
             const gc_adam_hyper& h = job->adam;
             GC_REQUIRE(job->out_maps, GC_E_INVAL, "fit job needs out_maps");
             if ((rc = validate_adam(m, &h))) return rc;
+            GC_REQUIRE(h.t_start == 0 && !h.init_state && !h.final_state, GC_E_INVAL,
+                       "checkpoint / resume (t_start, init_state, final_state) is a "
+                       "gc_fit_askadam option, not a server job's");
         } else {
             set_error("unknown job kind");
             return GC_E_INVAL;

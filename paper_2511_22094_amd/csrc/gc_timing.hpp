@@ -17,6 +17,8 @@ struct LaunchTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     hipEvent_t pending = nullptr;
     int64_t count = 0;       // launches seen (timed or not)
+    void* ref = nullptr;     // the device's trace reference event (GACELLE_TRACE)
+    int dev = 0;
     LaunchTimer(const char* fam, hipStream_t st) : family(fam), s(st) {}
     void begin();
     void end();

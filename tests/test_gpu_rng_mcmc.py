@@ -134,38 +134,50 @@ def _mh_fp64_bit_exact(orc, d, model, shape, kw):
 def test_mh_fp32_register_variants_follow_oracle_chains(orc, model, te):
     """The FP32 kernels (data in registers: one instantiation per echo count,
     guarded or straight-line, recurrence or direct; dwi2 reads memory) follow the FP64
-    oracle's chains decision for decision wherever the oracle's decisions
-    are far from ties: chains start at the truth, so log-likelihoods are
-    O(M) and their FP32 error (below 1e-3 nats at the 99th percentile for
-    gre3) stays under the 0.005-nat margin required.  Steps are scaled to
-    about a third accepted.  A wrong likelihood would part the chains at
-    once."""
+    oracle's chains decision for decision up to the first decision the oracle
+    takes within 0.005 nats of a tie: chains start at the truth, so
+    log-likelihoods are O(M) and their FP32 error (below 1e-3 nats at the
+    99th percentile for gre3) stays under that margin.  Every voxel is
+    compared over the longest prefix (100 iterations down to 2) on which all
+    of its oracle decisions are that far from ties -- the prefixes are shorter
+    runs of the same chains -- so a voxel with a near tie is still checked up
+    to it.  Steps are scaled to about a third accepted.  A wrong likelihood
+    would part the chains at once."""
     rng = np.random.default_rng(77)
     shape = (3, 8, 10)
     mask = (rng.uniform(size=shape) < 0.9).astype(np.uint8)
     acq = None if te is None else synth.Acq(te=np.asarray(te, float))
     d = synth.make_draw(model, shape, 21, 0.02 if model == "dwi2" else 0.01, acq=acq, mask=mask)
     y, yg = _data(orc, d)
-    C, kw = 2, dict(n_iter=100, burnin=50, thin=5)
+    C = 2
     scale = {"gre3": 0.2, "dwi2": 0.3, "linear3": 0.3}.get(model, 1.0)
     step = scale * np.asarray(synth.MH_STEP[model])
     x0 = d.truth.astype(np.float32)
-    ref = orc.mh(model, d.acq, y, d.lb, d.ub, step, d.sigma, 13, C,
-                 x0=np.broadcast_to(x0.astype(np.float64), (C,) + x0.shape), **kw)
-    out = G().gc_mcmc(_model(d), yg, d.mask, d.lb, d.ub, C, sigma=d.sigma, step=step, seed=13,
-                      x0_map=synth.scatter(x0, d.mask), x0_mode="given", final_state=True, **kw)
-    far = ref["margin"] > 0.005
-    say("fp32 variants", model, d.acq.n_meas, "far from ties:", far.mean(),
-        "accepted", ref["accept"].mean() / kw["n_iter"])
-    assert far.mean() > 0.6
-    acc = synth.gather(out["accept"], d.mask)
-    assert np.array_equal(acc[:, far], ref["accept"][:, far])
+    x0c = np.broadcast_to(x0.astype(np.float64), (C,) + x0.shape)
     rng_ = (d.ub - d.lb)[None, :, None]
-    fin = out["final_state"].reshape(d.n_params, C, d.n).transpose(1, 0, 2)
-    err = np.abs(fin - ref["final"]) / rng_
-    assert err[:, :, far].max() < 1e-4
-    merr = np.abs(synth.gather(out["mean"], d.mask) - ref["mean"]) / rng_[0]
-    assert merr[:, far].max() < 1e-4
+    covered = np.zeros(d.n, bool)
+    report = []
+    for T in (100, 60, 35, 20, 12, 7, 4, 2):   # a call keeps >= 2 samples per chain
+        kw = dict(n_iter=T, burnin=50, thin=5) if T == 100 else dict(n_iter=T, burnin=0, thin=1)
+        ref = orc.mh(model, d.acq, y, d.lb, d.ub, step, d.sigma, 13, C, x0=x0c, **kw)
+        out = G().gc_mcmc(_model(d), yg, d.mask, d.lb, d.ub, C, sigma=d.sigma, step=step,
+                          seed=13, x0_map=synth.scatter(x0, d.mask), x0_mode="given",
+                          final_state=True, **kw)
+        far = ref["margin"] > 0.005
+        acc = synth.gather(out["accept"], d.mask)
+        assert np.array_equal(acc[:, far], ref["accept"][:, far]), T
+        fin = out["final_state"].reshape(d.n_params, C, d.n).transpose(1, 0, 2)
+        assert (np.abs(fin - ref["final"]) / rng_)[:, :, far].max(initial=0) < 1e-4, T
+        merr = np.abs(synth.gather(out["mean"], d.mask) - ref["mean"]) / rng_[0]
+        assert merr[:, far].max(initial=0) < 1e-4, T
+        report.append((T, int((far & ~covered).sum())))
+        covered |= far
+        if covered.all():
+            break
+    say("fp32 variants", model, d.acq.n_meas, "voxels first covered at prefix length:", report,
+        "never:", int((~covered).sum()), "of", d.n)
+    # only a near tie in a voxel's very first decisions leaves it unchecked
+    assert covered.mean() >= 0.98
 
 
 def test_mh_uniform_init_fp64_bit_exact(orc):
@@ -315,6 +327,8 @@ def test_ensemble_fp32_gre3_matches_oracle(orc):
     _ensemble_fp32_vs_fp64(orc, d, 20, dict(n_iter=1500, burnin=300, thin=5), "gre3 fp32")
 
 
+@pytest.mark.parametrize("model,walkers", [("gre3", 16), ("dwi2", 4), ("dwi2", 16)],
+                         ids=["gre3-16-lds-pairs", "dwi2-4-memory", "dwi2-16-lds"])
 def test_ensemble_fp64_bit_exact_other_models(orc, model, walkers):
     """The ensemble kernel's two data paths: measurements staged in LDS (as
     (re, im) pairs for the complex model) and, when they would not fit beside

@@ -120,7 +120,10 @@ def test_replay_detects_a_planted_lifetime_mistake(harness):
                    "            rec.dev = nullptr;\n"
                    "            inflight.push_back(std::move(rec));")
     rc, out = _replay(exe, d / "trace64.txt", "--saturated", delay=300)
-    assert rc != 0 and "VIOLATION" in out and "freed arena memory" in out, out[-3000:]
+    # the released block is either still free when a stub reads it, or
+    # already handed to a later allocation: both are reported
+    early = ("freed arena memory", "allocation made after the launch was enqueued")
+    assert rc != 0 and "VIOLATION" in out and any(e in out for e in early), out[-3000:]
 
 
 def test_replay_shows_failed_round_must_wait_for_earlier_rounds(harness):
