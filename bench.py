@@ -71,13 +71,17 @@ MH_GRE3_MIX_CEILING = FLOP_PER_MH_STEP_GRE3 * 64 / MH_GRE3_ISSUE_CYCLES / 64.0  
 # WRITE_SIZE likewise.  A figure holds only for the kernel sources it was
 # taken on: when their sha256 differs, `traffic` is reported as null.
 MEASURED_TRAFFIC = {
+    "mh_chunk_cfg4": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
+        "sha256": "56798b367dbf8c20894cc721d3e608f65bd43c97414c2db16454f91a0d6d54fb",
+        "read_bytes": 3767460959, "write_bytes": 1804631552,
+        "profile": "profiles/mh_chunk_gre3_240x240x180_ellipsoid_8chains.md"},
     "mh_chunk_cfg1": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "fe6f1fb42a67f76b64a416d0457d3f1204c1d150362d1f4428856f8c579ab550",
-        "read_bytes": 1595949552, "write_bytes": 788529152,
+        "sha256": "56798b367dbf8c20894cc721d3e608f65bd43c97414c2db16454f91a0d6d54fb",
+        "read_bytes": 1595957473, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
     "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "d7f72d664c4d10908f529d2df20c4d4e1349c3d92551a34789ccffbf819b6759",
-        "read_bytes": 127206688, "write_bytes": 15728648,
+        "sha256": "f09dbc8d6dc65ae300cef49345ecb5e3a56e7594c5c646eec5be09881e3face2",
+        "read_bytes": 126895011, "write_bytes": 15728640,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
         "sha256": "507f17098a9bed05bcd421ada5ce1b058d15134190b3f264f043e7f27f45a22c",
