@@ -84,12 +84,12 @@ MEASURED_TRAFFIC = {
         "read_bytes": 126895011, "write_bytes": 15728640,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "507f17098a9bed05bcd421ada5ce1b058d15134190b3f264f043e7f27f45a22c",
-        "read_bytes": 112252178, "write_bytes": 100663321,
+        "sha256": "c6eb6184481b65f8ef0677579638a635744edc1f5b434efb036391502897e4aa",
+        "read_bytes": 112251863, "write_bytes": 100663296,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "507f17098a9bed05bcd421ada5ce1b058d15134190b3f264f043e7f27f45a22c",
-        "read_bytes": 147782953, "write_bytes": 111472117,
+        "sha256": "c6eb6184481b65f8ef0677579638a635744edc1f5b434efb036391502897e4aa",
+        "read_bytes": 147692825, "write_bytes": 111472128,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
@@ -704,6 +704,9 @@ SERVE_TRACES = {
     "full": (256, (1e3, 1e6), (1000, 10000), (200, 500)),
     # a smaller trace of the same mix (voxels up to 1e5, MCMC up to 4k iterations)
     "small": (64, (1e3, 1e5), (1000, 4000), (200, 500)),
+    # the same mix of 256 jobs with voxel counts of single slices and ROIs
+    # (log-uniform in [1e2, 1e4]): no job fills the GPU on its own
+    "small_jobs": (256, (1e2, 1e4), (1000, 10000), (200, 500)),
 }
 
 
@@ -957,10 +960,12 @@ def main():
         nxt = next_rows_leg(g, torch)
         for k, v in nxt.items():
             log(f"bench:   {k}: {v['value']:.3e} {v['unit']}, frac {v['roofline']['frac']:.3f}")
-    serve = None
+    serve = serve_small = None
     if not args.no_serve:
         serve = serve_leg(g, torch, args.serve_trace,
                           tuple(x for x in args.serve_legs.split(",") if x))
+        if args.serve_trace == "full":
+            serve_small = serve_leg(g, torch, "small_jobs", ("saturated",))
     cpu = oracle_err = adam_err = sense_err = None
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
@@ -1051,6 +1056,8 @@ def main():
         out["next_rows"] = nxt
     if serve is not None:
         out["serving"] = serve
+    if serve_small is not None:
+        out["serving_small_jobs"] = serve_small
     print(json.dumps(out))
 
 
