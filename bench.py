@@ -729,7 +729,7 @@ def serve_leg(g, torch, trace="full", legs=("saturated", "paced")):
         for mode in ("batched", "baseline"):
             log(f"bench: serving {leg} {mode}")
             res[mode], dig[mode] = serve_run(g, jobs, mode == "baseline", sat)
-            log(f"bench:   {res[mode]}")
+            log(f"bench:   { {k: v for k, v in res[mode].items() if k not in ('latencies', 'work')} }")
         res["speedup"] = res["batched"]["value"] / res["baseline"]["value"]
         res["identical_results"] = dig["batched"] == dig["baseline"]
         if sat:

@@ -127,6 +127,14 @@ struct gc_server {
     std::vector<gc::Job*> resident;
     size_t used = 0;
     hipStream_t prep = nullptr, compute = nullptr, copy = nullptr;
+    // launch lanes of a round (batched mode): the groups of a round run on
+    // these streams side by side, fenced by `lane_start` (after the round's
+    // descriptor upload on `compute`) and `lane_end` (joined back into
+    // `compute` before the round's completion event)
+    static constexpr int kLanes = 4;
+    hipStream_t lane[kLanes] = {};
+    hipEvent_t lane_start = nullptr;
+    hipEvent_t lane_end[kLanes] = {};
     gc::PinnedPool pinned;
     gc::DevArena arena;              // all device memory of resident jobs and rounds
     // statistics
@@ -555,19 +563,65 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
         std::memcpy(host + u.om, u.g->map.data(), u.g->map.size() * sizeof(BlkMap));
     }
     GC_TRY_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, S->compute));
+    // Streams of the round's launches.  One-job-per-launch mode keeps every
+    // launch on `compute`.  Batched mode spreads the groups (each holds
+    // different jobs) over lanes 1.. by largest work first onto the least
+    // loaded lane, and runs the per-iteration fit steps, which must stay in
+    // order, on lane 0; every lane starts after the upload and is joined
+    // back into `compute` on every exit from here, so the round's event
+    // (recorded on `compute` by the caller) still covers all its launches.
+    struct LaneJoin {
+        gc_server* S = nullptr;
+        ~LaneJoin() {
+            if (!S) return;
+            for (int k = 0; k < gc_server::kLanes; ++k) {
+                (void)hipEventRecord(S->lane_end[k], S->lane[k]);
+                (void)hipStreamWaitEvent(S->compute, S->lane_end[k], 0);
+            }
+        }
+    } join;
+    const bool lanes = !S->cfg.baseline;
+    std::vector<hipStream_t> gstream(groups.size(), S->compute);
+    hipStream_t step_stream = S->compute;
+    if (lanes) {
+        GC_TRY_HIP(hipEventRecord(S->lane_start, S->compute));
+        join.S = S;
+        for (int k = 0; k < gc_server::kLanes; ++k)
+            GC_TRY_HIP(hipStreamWaitEvent(S->lane[k], S->lane_start, 0));
+        std::vector<double> work(groups.size(), 0.0);
+        for (size_t i = 0; i < groups.size(); ++i) {
+            const Group& g = groups[i];
+            for (const MhJob& q : g.mh) work[i] += (double)q.n * q.C * (q.t1 - q.t0);
+            for (const FitJob& q : g.fit) work[i] += (double)q.n * (q.t1 - q.t0 + 1);
+        }
+        std::vector<size_t> order(groups.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work[a] > work[b]; });
+        double load[gc_server::kLanes] = {};
+        for (size_t i : order) {
+            int best = 1;
+            for (int k = 2; k < gc_server::kLanes; ++k)
+                if (load[k] < load[best]) best = k;
+            load[best] += work[i];
+            gstream[i] = S->lane[best];
+        }
+        step_stream = S->lane[0];
+    }
     size_t ui = 0;
-    for (auto& g : groups) {
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        Group& g = groups[gi];
         Up& u = ups[ui++];
         const int nb = (int)g.map.size();
         const BlkMap* mp = (const BlkMap*)(dev + u.om);
+        const hipStream_t st = gstream[gi];
         // timed launches are read out when the round has completed
         timers.push_back(std::make_unique<LaunchTimer>(
-            g.kernel == 0 ? "mh_chunk" : (g.kernel == 1 ? "fit_fused" : "ens_chunk"), S->compute));
+            g.kernel == 0 ? "mh_chunk" : (g.kernel == 1 ? "fit_fused" : "ens_chunk"), st));
         LaunchTimer& tm = *timers.back();
         tm.begin();
-        if (g.kernel == 0) GC_TRY_HIP(mh_chunk(g.kind, g.fp64, g.maxm, (const MhJob*)(dev + u.od), mp, nb, g.walkers, g.meff, S->compute));
-        else if (g.kernel == 1) GC_TRY_HIP(fit_fused(g.kind, g.maxm, (const FitJob*)(dev + u.od), mp, nb, S->compute));
-        else GC_TRY_HIP(ens_chunk_walkers(g.kind, g.fp64, (const MhJob*)(dev + u.od), mp, nb, g.walkers, g.meff, S->compute));
+        if (g.kernel == 0) GC_TRY_HIP(mh_chunk(g.kind, g.fp64, g.maxm, (const MhJob*)(dev + u.od), mp, nb, g.walkers, g.meff, st));
+        else if (g.kernel == 1) GC_TRY_HIP(fit_fused(g.kind, g.maxm, (const FitJob*)(dev + u.od), mp, nb, st));
+        else GC_TRY_HIP(ens_chunk_walkers(g.kind, g.fp64, (const MhJob*)(dev + u.od), mp, nb, g.walkers, g.meff, st));
         tm.end();
     }
     for (auto& gs : steps) {
@@ -575,9 +629,9 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
             Up& u = ups[ui++];
             const int nb = (int)g.map.size();
             const FitJob* dj = (const FitJob*)(dev + u.od);
-            timers.push_back(std::make_unique<LaunchTimer>("fit_step", S->compute));
+            timers.push_back(std::make_unique<LaunchTimer>("fit_step", step_stream));
             timers.back()->begin();
-            GC_TRY_HIP(fit_step(g.kind, dj, (const BlkMap*)(dev + u.om), nb, 1, S->compute));
+            GC_TRY_HIP(fit_step(g.kind, dj, (const BlkMap*)(dev + u.om), nb, 1, step_stream));
             timers.back()->end();
             for (size_t k = 0; k < g.fit.size(); ++k) {
                 if (!g.fit[k].record) continue;
@@ -586,7 +640,7 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
                 const int t = g.iter[k];
                 GC_TRY_HIP(fit_loss_stop(g.fit[k].partial, J->nblk, J->hist, t,
                                          h.tol > 0 ? h.tol : -INFINITY, h.conv_value,
-                                         h.conv_window, J->stop, S->compute));
+                                         h.conv_window, J->stop, step_stream));
             }
         }
     }
@@ -931,6 +985,11 @@ int gc_server_create(const gc_server_cfg* cfg, gc_server** out) {
         GC_TRY_HIP(hipStreamCreateWithFlags(&S->prep, hipStreamNonBlocking));
         GC_TRY_HIP(hipStreamCreateWithFlags(&S->compute, hipStreamNonBlocking));
         GC_TRY_HIP(hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking));
+        GC_TRY_HIP(hipEventCreateWithFlags(&S->lane_start, hipEventDisableTiming));
+        for (int k = 0; k < gc_server::kLanes; ++k) {
+            GC_TRY_HIP(hipStreamCreateWithFlags(&S->lane[k], hipStreamNonBlocking));
+            GC_TRY_HIP(hipEventCreateWithFlags(&S->lane_end[k], hipEventDisableTiming));
+        }
         gc_server* raw = S.release();
         raw->thr = std::thread(scheduler, raw);
         *out = raw;
@@ -1090,6 +1149,12 @@ int gc_server_destroy(gc_server* S) {
     (void)hipStreamSynchronize(S->compute);
     (void)hipStreamSynchronize(S->copy);
     (void)hipStreamSynchronize(S->prep);
+    for (int k = 0; k < gc_server::kLanes; ++k) {
+        (void)hipStreamSynchronize(S->lane[k]);
+        (void)hipStreamDestroy(S->lane[k]);
+        (void)hipEventDestroy(S->lane_end[k]);
+    }
+    (void)hipEventDestroy(S->lane_start);
     (void)hipStreamDestroy(S->prep);
     (void)hipStreamDestroy(S->compute);
     (void)hipStreamDestroy(S->copy);

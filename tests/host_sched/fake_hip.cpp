@@ -472,6 +472,11 @@ hipError_t hipStreamSynchronize(hipStream_t s) {
     return hipSuccess;
 }
 
+hipError_t hipDeviceSynchronize(void) {
+    drain_all();
+    return hipSuccess;
+}
+
 hipError_t hipEventCreate(hipEvent_t* e) {
     auto ev = std::make_shared<ihipEvent_t>();
     std::lock_guard<std::mutex> lk(g_reg_mu);

@@ -149,3 +149,15 @@ def test_replay_shows_failed_round_must_wait_for_earlier_rounds(harness):
     rc, out = _replay(exe, d / "trace64.txt", "--saturated", "--expect-failures", delay=1000,
                       extra_env={"HH_FAIL_LAUNCH": "mh_chunk:7"})
     assert rc != 0 and "VIOLATION" in out, out[-3000:]
+
+
+def test_replay_detects_lanes_not_joined_into_the_round(harness):
+    """A copy of the scheduler whose round event does not wait for the launch
+    lanes: the event can complete while groups still run on the lanes, and
+    the descriptors and arrays it guards go back to the arena under them."""
+    d, _, objs = harness
+    exe = _planted(d, objs, "unjoined_lanes",
+                   "                (void)hipStreamWaitEvent(S->compute, S->lane_end[k], 0);",
+                   "                (void)S->lane_end[k];")
+    rc, out = _replay(exe, d / "trace64.txt", "--saturated", delay=300)
+    assert rc != 0 and "VIOLATION" in out, out[-3000:]
