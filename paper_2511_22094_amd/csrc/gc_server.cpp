@@ -147,7 +147,11 @@ namespace gc {
 
 namespace {
 
-constexpr int kFitStepRound = 25;   // iterations per round for per-iteration fits
+// iterations per round of per-iteration (TV / stopping-rule) fits: 25 when
+// every launch of a round shares one stream; with launch lanes the steps run
+// beside the round's other groups, and a fifth of the MCMC chunk keeps them
+// from needing many more rounds than the chains they share the GPU with
+constexpr int kFitStepRound = 25;
 
 size_t footprint_of(const gc_model* m, const gc_job& j, int64_t G, int64_t n) {
     size_t b = (size_t)G * m->Meff * 4 + (size_t)G * 9 + (size_t)n * m->Meff * 4 +
@@ -491,7 +495,8 @@ static int launch_round(gc_server* S, int round, std::vector<Job*>& active, void
     }
     // per-iteration groups for step-path fits
     std::vector<std::vector<Group>> steps;
-    for (int s = 0; s < kFitStepRound; ++s) {
+    const int step_round = S->cfg.baseline ? kFitStepRound : std::max(kFitStepRound, chunk / 5);
+    for (int s = 0; s < step_round; ++s) {
         std::vector<Group> gs;
         for (Job* J : stepjobs) {
             const int t = J->t_next + 1;

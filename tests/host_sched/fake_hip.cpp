@@ -75,7 +75,10 @@ size_t env_size(const char* k, size_t dflt) {
     const char* v = std::getenv(k);
     return v ? (size_t)std::strtoull(v, nullptr, 10) : dflt;
 }
-const size_t kCopyCap = env_size("HH_COPY_CAP", (size_t)8 << 20);   // larger copies: ranges only
+// copies up to this size move their bytes (every descriptor upload of a round
+// among them: the kernel stubs read the descriptors); larger ones, bulk data
+// the stubs never read, are checked by range only
+const size_t kCopyCap = env_size("HH_COPY_CAP", (size_t)64 << 20);
 const unsigned kDelayUs = (unsigned)env_size("HH_DELAY_US", 100);
 
 double now() {
