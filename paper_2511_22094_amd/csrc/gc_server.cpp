@@ -131,7 +131,7 @@ struct gc_server {
     // these streams side by side, fenced by `lane_start` (after the round's
     // descriptor upload on `compute`) and `lane_end` (joined back into
     // `compute` before the round's completion event)
-    static constexpr int kLanes = 4;
+    static constexpr int kLanes = 8;
     hipStream_t lane[kLanes] = {};
     hipEvent_t lane_start = nullptr;
     hipEvent_t lane_end[kLanes] = {};
