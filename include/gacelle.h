@@ -204,6 +204,13 @@ typedef struct {
     int t_start;              /* iterations already run (0 = fresh start) */
     const float *init_state;  /* [3][P][n_masked] state after t_start (t_start > 0) */
     float *final_state;       /* [3][P][n_masked] state after the last iteration, or NULL */
+    /* Arithmetic: GC_PREC_FP32 (0, production) or GC_PREC_FP64 (1), the
+     * deterministic test path: the per-iteration kernels with the iterate,
+     * moments, bias corrections and losses in FP64 (data stay FP32 inputs;
+     * out_maps receives theta rounded once to FP32).  FP64 runs one launch
+     * per iteration whatever the regulariser and takes no checkpoint /
+     * resume fields. */
+    int precision;
 } gc_adam_hyper;
 
 typedef struct {

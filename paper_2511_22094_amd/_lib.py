@@ -80,7 +80,7 @@ class gc_adam_hyper(ctypes.Structure):
                 ("graph_nnz", c_int64), ("graph_rowptr", c_void_p), ("graph_col", c_void_p),
                 ("prior_lambda", c_double), ("prior_mask", c_uint32), ("prior_mu", c_void_p),
                 ("prior_sigma", c_void_p), ("t_start", c_int), ("init_state", c_void_p),
-                ("final_state", c_void_p)]
+                ("final_state", c_void_p), ("precision", c_int)]
 
 
 TV_KINDS = {"aniso": 0, "iso": 1, "graph": 2}
@@ -388,7 +388,7 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
                    tv_dim=3, tol=0.0, conv_value=0.0, conv_window=20, loss_history=False,
                    out=None, tv_kind="aniso", graph=None, prior_lam=0.0,
                    prior_params: Sequence[int] = (), prior_mu=None, prior_sigma=None,
-                   t_start=0, init_state=None, final_state=False):
+                   t_start=0, init_state=None, final_state=False, precision="fp32"):
     """Returns dict(maps [P, nz, ny, nx] float32, iters_run, final_loss, stop_reason[, loss]
     [, final_state]).
 
@@ -400,7 +400,10 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
     [3, P, n_masked] float32 (u, m, v) after the last iteration; t_start > 0
     with init_state = that state of a call that ran t_start iterations runs
     iterations t_start + 1 .. n_iter.  loss_history may then be the earlier
-    call's losses (their first t_start entries seed the convergence window)."""
+    call's losses (their first t_start entries seed the convergence window).
+
+    precision "fp64": the deterministic test path (FP64 iterate, moments and
+    losses, one launch per iteration; maps rounded once to FP32)."""
     a = _Args()
     nx, ny, nz = _shape3(y, model)
     vol = gc_volume(nx, ny, nz, a.ptr(y, np.float32))
@@ -431,6 +434,7 @@ def gc_fit_askadam(model: Model, y, mask, lb, ub, *, x0=None, x0_map=None, weigh
     mo = a.out(maps, np.float32)
     h.t_start = int(t_start)
     h.init_state = a.ptr(init_state, np.float32)
+    h.precision = {"fp32": 0, "fp64": 1}[precision]
     fs = None
     if final_state:
         if mask is None:

@@ -466,6 +466,24 @@ int fill_fit_job(const gc_model* m, const gc_bounds* b, const gc_adam_hyper* h, 
     J->scale_data = (float)(1.0 / (N * m->Meff));
     J->scale_tv = (float)(h->lambda / N);
     J->scale_prior = (float)(h->prior_lambda / N);
+    // the same constants unrounded, for the FP64 instantiation
+    for (int p = 0; p < m->P; ++p) {
+        const double lo = b->lb[p], hi = b->ub[p];
+        J->lbd[p] = lo;
+        J->rngd[p] = hi - lo;
+        const double x0 = b->x0 ? b->x0[p] : 0.5 * (lo + hi);
+        J->u0d[p] = (x0 - lo) / (hi - lo);
+    }
+    J->lrd = h->lr;
+    J->epsd = h->eps;
+    J->momentumd = h->momentum;
+    J->rhod = h->rho;
+    J->omb1d = 1.0 - h->beta1;
+    J->omb2d = 1.0 - h->beta2;
+    J->omrhod = 1.0 - h->rho;
+    J->scale_datad = 1.0 / (N * m->Meff);
+    J->scale_tvd = h->lambda / N;
+    J->scale_priord = h->prior_lambda / N;
     J->active = 1;
     J->acq = acq;
     return GC_OK;
@@ -505,6 +523,11 @@ int validate_adam(const gc_model* m, const gc_adam_hyper* h) {
     GC_REQUIRE(h->t_start == 0 || !(h->conv_value > 0) || h->loss_history, GC_E_INVAL,
                "resume with a convergence window needs loss_history holding the first "
                "t_start losses");
+    GC_REQUIRE(h->precision == GC_PREC_FP32 || h->precision == GC_PREC_FP64, GC_E_INVAL,
+               "precision must be GC_PREC_FP32 or GC_PREC_FP64");
+    GC_REQUIRE(h->precision == GC_PREC_FP32 || (h->t_start == 0 && !h->init_state &&
+                                                !h->final_state),
+               GC_E_INVAL, "checkpoint / resume is an FP32 option");
     return GC_OK;
 }
 
@@ -747,7 +770,8 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
         const bool stopping = hyper->tol > 0 || hyper->conv_value > 0;
         const bool history = hyper->loss_history != nullptr;
         FitJob* djob = nullptr;
-        if (!tv && !stopping && !history) {
+        const bool f64 = hyper->precision == GC_PREC_FP64;
+        if (!f64 && !tv && !stopping && !history) {
             // fused path: the whole loop in registers, chunks of <= 1000 iterations
             const int chunk = 1000;
             const int nck = (T - t_start + chunk - 1) / chunk;
@@ -809,6 +833,16 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
             // the loss is reduced on every iteration only when a stopping rule or
             // the history needs it, else once, on the last iteration
             const bool each = stopping || history;
+            // FP64 instantiation: its own iterate, moments and loss partials
+            double *u0d = nullptr, *u1d = nullptr, *md = nullptr, *vd = nullptr,
+                   *partiald = nullptr;
+            if (f64) {
+                GC_TRY_HIP(sc.alloc_n(&u0d, np));
+                GC_TRY_HIP(sc.alloc_n(&u1d, np));
+                GC_TRY_HIP(sc.alloc_n(&md, np));
+                GC_TRY_HIP(sc.alloc_n(&vd, np));
+                GC_TRY_HIP(sc.alloc_n(&partiald, (size_t)nblk * (each ? T : 1)));
+            }
             GC_TRY_HIP(sc.alloc_n(&partial, (size_t)nblk * (each ? T : 1)));
             GC_TRY_HIP(sc.alloc_n(&hist, (size_t)T));
             GC_TRY_HIP(sc.alloc_n(&stop, 2));
@@ -821,18 +855,28 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
                 b2 *= hyper->beta2;
                 q.c1 = (float)(1.0 / (1.0 - b1));
                 q.c2 = (float)(1.0 / (1.0 - b2));
+                q.c1d = 1.0 / (1.0 - b1);
+                q.c2d = 1.0 / (1.0 - b2);
                 q.u = u0;   // fit_init writes here
                 q.u_in = (t % 2 == 1) ? u0 : u1;
                 q.u_out = (t % 2 == 1) ? u1 : u0;
+                q.ud = u0d;
+                q.u_ind = (t % 2 == 1) ? u0d : u1d;
+                q.u_outd = (t % 2 == 1) ? u1d : u0d;
+                q.md = md;
+                q.vd = vd;
                 q.nbr = nbr;
                 q.record = (each || t == T) ? 1 : 0;
                 q.partial = partial + (each ? (size_t)(t - 1) * nblk : 0);
+                q.partiald = f64 ? partiald + (each ? (size_t)(t - 1) * nblk : 0) : nullptr;
                 q.blk0 = 0;
                 q.stop = stop;
             }
             GC_TRY_HIP(sc.alloc_n(&djob, (size_t)T));
             GC_TRY_HIP(hipMemcpyAsync(djob, jobs.data(), T * sizeof(FitJob), hipMemcpyHostToDevice, s));
-            if (t_start == 0) {
+            if (f64) {
+                GC_TRY_HIP(fit_init_f64(djob, dmap, (int)nblk, s));
+            } else if (t_start == 0) {
                 GC_TRY_HIP(fit_init(djob, dmap, (int)nblk, s));
             } else {
                 // iteration t_start + 1 reads the iterate from its u_in buffer;
@@ -849,9 +893,13 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
             LaunchTimer tm("fit_step", s);
             for (int t = t_start + 1; t <= T; ++t) {
                 tm.begin();
-                GC_TRY_HIP(fit_step(model->kind, djob + (t - 1), dmap, (int)nblk, 1, s));
+                if (f64) GC_TRY_HIP(fit_step_f64(model->kind, djob + (t - 1), dmap, (int)nblk, 1, s));
+                else GC_TRY_HIP(fit_step(model->kind, djob + (t - 1), dmap, (int)nblk, 1, s));
                 tm.end();
-                if (jobs[t - 1].record)
+                if (jobs[t - 1].record && f64)
+                    GC_TRY_HIP(fit_loss_stop_f64(jobs[t - 1].partiald, nblk, hist, t, tol,
+                                                 hyper->conv_value, hyper->conv_window, stop, s));
+                else if (jobs[t - 1].record)
                     GC_TRY_HIP(fit_loss_stop(jobs[t - 1].partial, nblk, hist, t, tol,
                                              hyper->conv_value, hyper->conv_window, stop, s));
                 if (stopping && t % poll == 0 && t < T) {
@@ -878,7 +926,11 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
                 GC_TRY_HIP(hipStreamSynchronize(s));
             }
             float* ufin = (iters % 2 == 1) ? u1 : u0;
-            GC_TRY_HIP(fit_theta(P, J.lb, J.rng, ufin, n, theta_c, s));
+            if (f64)
+                GC_TRY_HIP(fit_theta_f64(P, J.lbd, J.rngd, (iters % 2 == 1) ? u1d : u0d, n,
+                                         theta_c, s));
+            else
+                GC_TRY_HIP(fit_theta(P, J.lb, J.rng, ufin, n, theta_c, s));
             if (hyper->final_state)
                 GC_TRY_HIP(copy_state(hyper->final_state, ufin, m, v, np, false, s));
         }

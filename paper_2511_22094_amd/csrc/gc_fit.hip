@@ -39,21 +39,22 @@ struct YGlob {
 //   LP = 1: loss += |r|, returns -sign(r)   (dLoss/ds = w (-sign r), loss w)
 // with r = y - s.  LP is a template parameter so that the measurement loops
 // carry no branch.
-template <class Y, int LP> struct DLoss {
+template <class Y, int LP, typename R = float> struct DLoss {
     const Y& y;
-    float loss;
-    __device__ __forceinline__ float one(float ym, float s) {
-        const float r = ym - s;
+    R loss;
+    __device__ __forceinline__ R one(R ym, R s) {
+        const R r = ym - s;
         if constexpr (LP == 2) {
             loss += r * r;
             return r;
         } else {
-            loss += fabsf(r);
-            return r > 0.f ? -1.f : (r < 0.f ? 1.f : 0.f);
+            if constexpr (sizeof(R) == 4) loss += fabsf(r);
+            else loss += fabs(r);
+            return r > (R)0 ? (R)-1 : (r < (R)0 ? (R)1 : (R)0);
         }
     }
-    __device__ __forceinline__ float re(int m, float s) { return one(y.re(m), s); }
-    __device__ __forceinline__ float im(int m, float s) { return one(y.im(m), s); }
+    __device__ __forceinline__ R re(int m, R s) { return one((R)y.re(m), s); }
+    __device__ __forceinline__ R im(int m, R s) { return one((R)y.im(m), s); }
 };
 
 // upstream gradient ds read from HBM (vector-Jacobian product)
@@ -77,50 +78,118 @@ struct SOut {
     __device__ __forceinline__ void im(int m, float x) { s[(int64_t)(M + m) * n + v] = x; }
 };
 
+// The descriptor's constants and arrays in the arithmetic of an
+// instantiation: FP32 (production) or FP64 (the deterministic test path of
+// the per-iteration shape).
+template <typename R> struct FitR;
+template <> struct FitR<float> {
+    static __device__ __forceinline__ float lb(const FitJob& J, int p) { return J.lb[p]; }
+    static __device__ __forceinline__ float rng(const FitJob& J, int p) { return J.rng[p]; }
+    static __device__ __forceinline__ float u0(const FitJob& J, int p) { return J.u0[p]; }
+    static __device__ __forceinline__ float lr(const FitJob& J) { return J.lr; }
+    static __device__ __forceinline__ float beta1(const FitJob& J) { return J.beta1; }
+    static __device__ __forceinline__ float beta2(const FitJob& J) { return J.beta2; }
+    static __device__ __forceinline__ float eps(const FitJob& J) { return J.eps; }
+    static __device__ __forceinline__ float momentum(const FitJob& J) { return J.momentum; }
+    static __device__ __forceinline__ float rho(const FitJob& J) { return J.rho; }
+    static __device__ __forceinline__ float omb1(const FitJob& J) { return J.omb1; }
+    static __device__ __forceinline__ float omb2(const FitJob& J) { return J.omb2; }
+    static __device__ __forceinline__ float omrho(const FitJob& J) { return J.omrho; }
+    static __device__ __forceinline__ float scale_data(const FitJob& J) { return J.scale_data; }
+    static __device__ __forceinline__ float scale_tv(const FitJob& J) { return J.scale_tv; }
+    static __device__ __forceinline__ float scale_prior(const FitJob& J) { return J.scale_prior; }
+    static __device__ __forceinline__ float c1(const FitJob& J) { return J.c1; }
+    static __device__ __forceinline__ float c2(const FitJob& J) { return J.c2; }
+    static __device__ __forceinline__ float* u(const FitJob& J) { return J.u; }
+    static __device__ __forceinline__ const float* u_in(const FitJob& J) { return J.u_in; }
+    static __device__ __forceinline__ float* u_out(const FitJob& J) { return J.u_out; }
+    static __device__ __forceinline__ float* m(const FitJob& J) { return J.m; }
+    static __device__ __forceinline__ float* v(const FitJob& J) { return J.v; }
+    static __device__ __forceinline__ float* partial(const FitJob& J) { return J.partial; }
+    static __device__ __forceinline__ float sqrt(float x) { return sqrtf(x); }
+    static __device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.f), 1.f); }
+};
+template <> struct FitR<double> {
+    static __device__ __forceinline__ double lb(const FitJob& J, int p) { return J.lbd[p]; }
+    static __device__ __forceinline__ double rng(const FitJob& J, int p) { return J.rngd[p]; }
+    static __device__ __forceinline__ double u0(const FitJob& J, int p) { return J.u0d[p]; }
+    static __device__ __forceinline__ double lr(const FitJob& J) { return J.lrd; }
+    static __device__ __forceinline__ double beta1(const FitJob& J) { return J.beta1d; }
+    static __device__ __forceinline__ double beta2(const FitJob& J) { return J.beta2d; }
+    static __device__ __forceinline__ double eps(const FitJob& J) { return J.epsd; }
+    static __device__ __forceinline__ double momentum(const FitJob& J) { return J.momentumd; }
+    static __device__ __forceinline__ double rho(const FitJob& J) { return J.rhod; }
+    static __device__ __forceinline__ double omb1(const FitJob& J) { return J.omb1d; }
+    static __device__ __forceinline__ double omb2(const FitJob& J) { return J.omb2d; }
+    static __device__ __forceinline__ double omrho(const FitJob& J) { return J.omrhod; }
+    static __device__ __forceinline__ double scale_data(const FitJob& J) { return J.scale_datad; }
+    static __device__ __forceinline__ double scale_tv(const FitJob& J) { return J.scale_tvd; }
+    static __device__ __forceinline__ double scale_prior(const FitJob& J) { return J.scale_priord; }
+    static __device__ __forceinline__ double c1(const FitJob& J) { return J.c1d; }
+    static __device__ __forceinline__ double c2(const FitJob& J) { return J.c2d; }
+    static __device__ __forceinline__ double* u(const FitJob& J) { return J.ud; }
+    static __device__ __forceinline__ const double* u_in(const FitJob& J) { return J.u_ind; }
+    static __device__ __forceinline__ double* u_out(const FitJob& J) { return J.u_outd; }
+    static __device__ __forceinline__ double* m(const FitJob& J) { return J.md; }
+    static __device__ __forceinline__ double* v(const FitJob& J) { return J.vd; }
+    static __device__ __forceinline__ double* partial(const FitJob& J) { return J.partiald; }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
+};
+
 // One optimiser update of one coordinate in u units, then the projection.
-__device__ __forceinline__ float opt_update(const FitJob& J, float u, float g, float& m,
-                                            float& v, float c1, float c2) {
-    float un;
+template <typename R = float>
+__device__ __forceinline__ R opt_update(const FitJob& J, R u, R g, R& m, R& v, R c1, R c2) {
+    using F = FitR<R>;
+    R un;
     if (J.optimizer == 0) {
-        m = J.beta1 * m + J.omb1 * g;
-        v = J.beta2 * v + J.omb2 * g * g;
-        un = u - J.lr * (m * c1) / (sqrtf(v * c2) + J.eps);
+        m = F::beta1(J) * m + F::omb1(J) * g;
+        v = F::beta2(J) * v + F::omb2(J) * g * g;
+        un = u - F::lr(J) * (m * c1) / (F::sqrt(v * c2) + F::eps(J));
     } else if (J.optimizer == 1) {
-        m = J.momentum * m - J.lr * g;
+        m = F::momentum(J) * m - F::lr(J) * g;
         un = u + m;
     } else {
-        v = J.rho * v + J.omrho * g * g;
-        un = u - J.lr * g / (sqrtf(v) + J.eps);
+        v = F::rho(J) * v + F::omrho(J) * g * g;
+        un = u - F::lr(J) * g / (F::sqrt(v) + F::eps(J));
     }
-    return fminf(fmaxf(un, 0.f), 1.f);
+    return F::clamp01(un);
 }
 
 // data term of one voxel: loss (scaled) and dL/du (scaled) at iterate u
-template <class Mdl, int MAXM, class Y>
-__device__ __forceinline__ float data_grad(const FitJob& J, const float* u, const Y& y, float w,
-                                           float* gu) {
+template <class Mdl, int MAXM, class Y, typename R = float>
+__device__ __forceinline__ R data_grad(const FitJob& J, const R* u, const Y& y, R w, R* gu) {
+    using F = FitR<R>;
     constexpr int P = Mdl::P;
-    float th[P], g[P];
+    R th[P], g[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) th[p] = J.lb[p] + J.rng[p] * u[p];
-    float loss, gs;   // loss and gradient factors of the voxel weight
+    for (int p = 0; p < P; ++p) th[p] = F::lb(J, p) + F::rng(J, p) * u[p];
+    R loss, gs;   // loss and gradient factors of the voxel weight
     if (J.loss_p == 2) {
-        DLoss<Y, 2> d{y, 0.f};
+        DLoss<Y, 2, R> d{y, (R)0};
         Mdl::template grad<MAXM>(th, d, J.acq, g);
         loss = d.loss * (w * w);
-        gs = -2.f * (w * w);
+        gs = (R)-2 * (w * w);
     } else {
-        DLoss<Y, 1> d{y, 0.f};
+        DLoss<Y, 1, R> d{y, (R)0};
         Mdl::template grad<MAXM>(th, d, J.acq, g);
         loss = d.loss * w;
         gs = w;
     }
 #pragma unroll
-    for (int p = 0; p < P; ++p) gu[p] = J.rng[p] * (g[p] * (gs * J.scale_data));
-    return loss * J.scale_data;
+    for (int p = 0; p < P; ++p) gu[p] = F::rng(J, p) * (g[p] * (gs * F::scale_data(J)));
+    return loss * F::scale_data(J);
 }
 
-__device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+template <typename R> __device__ __forceinline__ R sgn(R x) {
+    return x > (R)0 ? (R)1 : (x < (R)0 ? (R)-1 : (R)0);
+}
+__device__ __forceinline__ float sgnf(float x) { return sgn(x); }
+
+template <typename T> __device__ __forceinline__ T absr(T x) {
+    if constexpr (sizeof(T) == 4) return fabsf(x);
+    else return fabs(x);
+}
 
 // Anisotropic grid TV at voxel v for one map up (iterate t-1): the pairs
 // (v, forward neighbour) add |difference| to R; the subgradient collects the
@@ -128,21 +197,22 @@ __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f
 // Neighbour values are read unconditionally (a missing neighbour, index -1,
 // reads element 0 and is then ignored) so that all reads of a voxel are in
 // flight together instead of one conditional read waiting after another.
-__device__ __forceinline__ float tv_aniso_at(const float* __restrict__ up, float uv,
-                                             const int32_t (&nb)[6], float& R) {
-    float un[6];
+template <typename T = float>
+__device__ __forceinline__ T tv_aniso_at(const T* __restrict__ up, T uv, const int32_t (&nb)[6],
+                                         T& R) {
+    T un[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) un[d] = gload(up)[nb[d] >= 0 ? nb[d] : 0];
-    float g = 0.f;
+    T g = 0;
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         const bool in = nb[d] >= 0;
         if (d & 1) {          // forward neighbour: pair (v, nb)
-            const float diff = in ? un[d] - uv : 0.f;
-            R += fabsf(diff);
-            g -= sgnf(diff);
+            const T diff = in ? un[d] - uv : (T)0;
+            R += absr(diff);
+            g -= sgn(diff);
         } else {              // backward neighbour: pair (nb, v)
-            g += in ? sgnf(uv - un[d]) : 0.f;
+            g += in ? sgn(uv - un[d]) : (T)0;
         }
     }
     return g;
@@ -153,11 +223,11 @@ __device__ __forceinline__ float tv_aniso_at(const float* __restrict__ up, float
 // each backward neighbour b, (u_v - u_b) / G_b from b's norm.  G_b needs b's
 // other forward neighbours: dg[d][e] is the forward neighbour along axis e of
 // the backward neighbour along axis d (dg[d][d] is v itself, unused).
-__device__ __forceinline__ float tv_iso_at(const float* __restrict__ up, float uv,
-                                           const int32_t (&nb)[6], const int32_t (&dg)[3][3],
-                                           float& R) {
+template <typename T = float>
+__device__ __forceinline__ T tv_iso_at(const T* __restrict__ up, T uv, const int32_t (&nb)[6],
+                                       const int32_t (&dg)[3][3], T& R) {
     // all neighbour values first (unconditional reads, see tv_aniso_at)
-    float uf[3], ubk[3], ud[3][3];
+    T uf[3], ubk[3], ud[3][3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         uf[d] = gload(up)[nb[2 * d + 1] >= 0 ? nb[2 * d + 1] : 0];
@@ -165,36 +235,36 @@ __device__ __forceinline__ float tv_iso_at(const float* __restrict__ up, float u
 #pragma unroll
         for (int e = 0; e < 3; ++e) ud[d][e] = gload(up)[dg[d][e] >= 0 ? dg[d][e] : 0];
     }
-    float D[3], ss = 0.f;
+    T D[3], ss = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        D[d] = nb[2 * d + 1] >= 0 ? uf[d] - uv : 0.f;
+        D[d] = nb[2 * d + 1] >= 0 ? uf[d] - uv : (T)0;
         ss += D[d] * D[d];
     }
-    const float Gv = sqrtf(ss);
+    const T Gv = FitR<T>::sqrt(ss);
     R += Gv;
-    float g = 0.f;
-    if (Gv > 0.f) {
+    T g = 0;
+    if (Gv > (T)0) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) g -= D[d] / Gv;
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (nb[2 * d] < 0) continue;
-        const float ub = ubk[d];
-        const float Dv = uv - ub;
-        float sb = 0.f;
+        const T ub = ubk[d];
+        const T Dv = uv - ub;
+        T sb = 0;
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             if (e == d) {
                 sb += Dv * Dv;
             } else if (dg[d][e] >= 0) {
-                const float t = ud[d][e] - ub;
+                const T t = ud[d][e] - ub;
                 sb += t * t;
             }
         }
-        const float Gb = sqrtf(sb);
-        if (Gb > 0.f) g += Dv / Gb;
+        const T Gb = FitR<T>::sqrt(sb);
+        if (Gb > (T)0) g += Dv / Gb;
     }
     return g;
 }
@@ -202,16 +272,16 @@ __device__ __forceinline__ float tv_iso_at(const float* __restrict__ up, float u
 // Graph TV at vertex v: R gains sum_{j in N(v)} |u_v - u_j|; with a symmetric
 // adjacency every edge also appears from j's side, so the subgradient is
 // 2 sum_j sign(u_v - u_j).
-__device__ __forceinline__ float tv_graph_at(const float* __restrict__ up, float uv,
-                                             const int64_t* __restrict__ rowptr,
-                                             const int32_t* __restrict__ col, int64_t v,
-                                             float& R) {
-    float g = 0.f;
+template <typename T = float>
+__device__ __forceinline__ T tv_graph_at(const T* __restrict__ up, T uv,
+                                         const int64_t* __restrict__ rowptr,
+                                         const int32_t* __restrict__ col, int64_t v, T& R) {
+    T g = 0;
     const int64_t k1 = rowptr[v + 1];
     for (int64_t k = rowptr[v]; k < k1; ++k) {
-        const float diff = uv - up[col[k]];
-        R += fabsf(diff);
-        g += 2.f * sgnf(diff);
+        const T diff = uv - up[col[k]];
+        R += absr(diff);
+        g += (T)2 * sgn(diff);
     }
     return g;
 }
@@ -219,19 +289,20 @@ __device__ __forceinline__ float tv_graph_at(const float* __restrict__ up, float
 // Prior term (Eq. 6) of one voxel: scale_prior |(theta - mu) / sigma| summed
 // over the parameters of prior_mask, added to the loss (returned) and its
 // subgradient in u units to gu.
-template <int P>
-__device__ __forceinline__ float prior_at(const FitJob& J, const float* u, const float* mu,
-                                          const float* sg, float* gu) {
-    float R = 0.f;
+template <int P, typename T = float>
+__device__ __forceinline__ T prior_at(const FitJob& J, const T* u, const T* mu, const T* sg,
+                                      T* gu) {
+    using F = FitR<T>;
+    T R = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (!((J.prior_mask >> p) & 1u)) continue;
-        const float th = J.lb[p] + J.rng[p] * u[p];
-        const float r = (th - mu[p]) / sg[p];
-        R += fabsf(r);
-        gu[p] += J.scale_prior * sgnf(r) * (J.rng[p] / sg[p]);
+        const T th = F::lb(J, p) + F::rng(J, p) * u[p];
+        const T r = (th - mu[p]) / sg[p];
+        R += absr(r);
+        gu[p] += F::scale_prior(J) * sgn(r) * (F::rng(J, p) / sg[p]);
     }
-    return J.scale_prior * R;
+    return F::scale_prior(J) * R;
 }
 
 }  // namespace
@@ -260,6 +331,31 @@ __global__ __launch_bounds__(kBlock) void fit_init_kernel(const FitJob* __restri
 
 hipError_t fit_init(const FitJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
     hipLaunchKernelGGL(fit_init_kernel, dim3(nblk), dim3(kBlock), 0, s, jobs, map);
+    return hipGetLastError();
+}
+
+// the same start in FP64: u = (x0 - lb) / (ub - lb) unrounded, clamped
+__global__ __launch_bounds__(kBlock) void fit_init_f64_kernel(const FitJob* __restrict__ jobs,
+                                                             const BlkMap* __restrict__ map) {
+    const BlkMap bm = map[blockIdx.x];
+    const FitJob& J = jobs[bm.job];
+    const int64_t v = bm.lane0 + threadIdx.x;
+    if (v >= J.n) return;
+    for (int p = 0; p < J.P; ++p) {
+        double u = J.u0d[p];
+        if (J.x0map) {
+            const double x = (double)J.x0map[(int64_t)p * J.n + v];
+            const double ub = J.lbd[p] + J.rngd[p];
+            u = fmin(fmax((x - J.lbd[p]) / (ub - J.lbd[p]), 0.0), 1.0);
+        }
+        J.ud[(int64_t)p * J.n + v] = u;
+        J.md[(int64_t)p * J.n + v] = 0.0;
+        J.vd[(int64_t)p * J.n + v] = 0.0;
+    }
+}
+
+hipError_t fit_init_f64(const FitJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(fit_init_f64_kernel, dim3(nblk), dim3(kBlock), 0, s, jobs, map);
     return hipGetLastError();
 }
 
@@ -361,13 +457,14 @@ hipError_t fit_fused(int kind, int maxm, const FitJob* jobs, const BlkMap* map, 
 // neighbour iterate gathers wait after it.  The data are read per use: a
 // register copy of all 96 dwi2 measurements cuts occupancy to three waves per
 // SIMD and measured 20 % slower at 64^3.
-template <int KIND>
+template <int KIND, typename R>
 __global__ __launch_bounds__(kBlock) void fit_step_kernel(const FitJob* __restrict__ jobs,
                                                          const BlkMap* __restrict__ map,
                                                          int nblk, int xcd_remap) {
-    using Mdl = typename ModelOf<KIND, float>::T;
+    using Mdl = typename ModelOf<KIND, R>::T;
+    using F = FitR<R>;
     constexpr int P = Mdl::P;
-    __shared__ float red[kBlock / 64];
+    __shared__ R red[kBlock / 64];
     int b = blockIdx.x;
     if (xcd_remap) {
         // hardware block b runs on XCD x = b % 8; XCD x takes the contiguous
@@ -381,14 +478,15 @@ __global__ __launch_bounds__(kBlock) void fit_step_kernel(const FitJob* __restri
     const int64_t n = J.n;
     const int64_t v = bm.lane0 + threadIdx.x;
     const bool live = v < n;
-    float contrib = 0.f;
+    R contrib = 0;
     if (live) {
-        float u[P], m[P], s2[P], gu[P];
+        const R* uin = F::u_in(J);
+        R u[P], m[P], s2[P], gu[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            u[p] = gload(J.u_in)[(int64_t)p * n + v];
+            u[p] = gload(uin)[(int64_t)p * n + v];
         }
-        const float w = J.w ? gload(J.w)[v] : 1.f;
+        const R w = J.w ? (R)gload(J.w)[v] : (R)1;
         const bool grid_tv = J.tv_mask && J.tv_kind != 2;
         int32_t nb[6], dg[3][3];
         if (grid_tv) {
@@ -406,50 +504,53 @@ __global__ __launch_bounds__(kBlock) void fit_step_kernel(const FitJob* __restri
             }
         }
         const YGlob yg{J.y, n, v, J.acq.M};
-        contrib = data_grad<Mdl, 0>(J, u, yg, w, gu);
+        contrib = data_grad<Mdl, 0, YGlob, R>(J, u, yg, w, gu);
         if (J.tv_mask) {
-            float R = 0.f;
+            R Rtv = 0;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!((J.tv_mask >> p) & 1u)) continue;
-                const float* up = J.u_in + (int64_t)p * n;
-                float g;
-                if (J.tv_kind == 0) g = tv_aniso_at(up, u[p], nb, R);
-                else if (J.tv_kind == 1) g = tv_iso_at(up, u[p], nb, dg, R);
-                else g = tv_graph_at(up, u[p], J.g_rowptr, J.g_col, v, R);
-                gu[p] += J.scale_tv * g;
+                const R* up = uin + (int64_t)p * n;
+                R g;
+                if (J.tv_kind == 0) g = tv_aniso_at<R>(up, u[p], nb, Rtv);
+                else if (J.tv_kind == 1) g = tv_iso_at<R>(up, u[p], nb, dg, Rtv);
+                else g = tv_graph_at<R>(up, u[p], J.g_rowptr, J.g_col, v, Rtv);
+                gu[p] += F::scale_tv(J) * g;
             }
-            contrib += J.scale_tv * R;
+            contrib += F::scale_tv(J) * Rtv;
         }
         if (J.prior_mask) {
-            float pmu[P], psg[P];
+            R pmu[P], psg[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const bool on = (J.prior_mask >> p) & 1u;
-                pmu[p] = on ? gload(J.mu)[(int64_t)p * n + v] : 0.f;
-                psg[p] = on ? gload(J.sigma)[(int64_t)p * n + v] : 1.f;
+                pmu[p] = on ? (R)gload(J.mu)[(int64_t)p * n + v] : (R)0;
+                psg[p] = on ? (R)gload(J.sigma)[(int64_t)p * n + v] : (R)1;
             }
-            contrib += prior_at<P>(J, u, pmu, psg, gu);
+            contrib += prior_at<P, R>(J, u, pmu, psg, gu);
         }
         // the optimiser state is read only now, so that it holds no registers
         // through the data term (84 instead of 96 VGPRs; measured 1 % faster
         // than reading it with the iterate, identical results)
+        R* mm = F::m(J);
+        R* vv = F::v(J);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            m[p] = gload(J.m)[(int64_t)p * n + v];
-            s2[p] = gload(J.v)[(int64_t)p * n + v];
+            m[p] = gload(mm)[(int64_t)p * n + v];
+            s2[p] = gload(vv)[(int64_t)p * n + v];
         }
+        R* uout = F::u_out(J);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const float un = opt_update(J, u[p], gu[p], m[p], s2[p], J.c1, J.c2);
-            J.u_out[(int64_t)p * n + v] = un;
-            J.m[(int64_t)p * n + v] = m[p];
-            J.v[(int64_t)p * n + v] = s2[p];
+            const R un = opt_update<R>(J, u[p], gu[p], m[p], s2[p], F::c1(J), F::c2(J));
+            uout[(int64_t)p * n + v] = un;
+            mm[(int64_t)p * n + v] = m[p];
+            vv[(int64_t)p * n + v] = s2[p];
         }
     }
     if (J.record) {
-        const float s = block_sum(contrib, red);
-        if (threadIdx.x == 0) J.partial[b - J.blk0] = s;
+        const R s = block_sum(contrib, red);
+        if (threadIdx.x == 0) F::partial(J)[b - J.blk0] = s;
     }
 }
 
@@ -457,8 +558,27 @@ hipError_t fit_step(int kind, const FitJob* jobs, const BlkMap* map, int nblk, i
                     hipStream_t s) {
 #define GC_STEP(K)                                                                      \
     case K:                                                                             \
-        hipLaunchKernelGGL((fit_step_kernel<K>), dim3(nblk), dim3(kBlock), 0, s, jobs, map, \
-                           nblk, xcd_remap);                                            \
+        hipLaunchKernelGGL((fit_step_kernel<K, float>), dim3(nblk), dim3(kBlock), 0, s, jobs, \
+                           map, nblk, xcd_remap);                                       \
+        break;
+    switch (kind) {
+        GC_STEP(MONOEXP_T2S)
+        GC_STEP(MONOEXP_R2S)
+        GC_STEP(GRE3)
+        GC_STEP(DWI2)
+        GC_STEP(LINEAR3)
+        default: return hipErrorInvalidValue;
+    }
+#undef GC_STEP
+    return hipGetLastError();
+}
+
+hipError_t fit_step_f64(int kind, const FitJob* jobs, const BlkMap* map, int nblk, int xcd_remap,
+                        hipStream_t s) {
+#define GC_STEP(K)                                                                      \
+    case K:                                                                             \
+        hipLaunchKernelGGL((fit_step_kernel<K, double>), dim3(nblk), dim3(kBlock), 0, s, jobs, \
+                           map, nblk, xcd_remap);                                       \
         break;
     switch (kind) {
         GC_STEP(MONOEXP_T2S)
@@ -743,7 +863,8 @@ namespace gc {
 //   losses against the iteration index| < conv, once t >= W.
 // stop[0] = stopping iteration (0 while running), stop[1] = reason.  Once
 // set, later iterations' kernels see stop[0] != 0 and do nothing.
-__global__ __launch_bounds__(kBlock) void fit_loss_stop_kernel(const float* __restrict__ partial,
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fit_loss_stop_kernel(const T* __restrict__ partial,
                                                               int64_t count,
                                                               double* __restrict__ hist, int t,
                                                               double tol, double conv, int W,
@@ -800,8 +921,15 @@ __global__ __launch_bounds__(kBlock) void fit_loss_stop_kernel(const float* __re
 
 hipError_t fit_loss_stop(const float* partial, int64_t count, double* hist, int t, double tol,
                          double conv, int W, int* stop, hipStream_t s) {
-    hipLaunchKernelGGL(fit_loss_stop_kernel, dim3(1), dim3(kBlock), 0, s, partial, count, hist, t,
-                       tol, conv, W, stop);
+    hipLaunchKernelGGL(fit_loss_stop_kernel<float>, dim3(1), dim3(kBlock), 0, s, partial, count,
+                       hist, t, tol, conv, W, stop);
+    return hipGetLastError();
+}
+
+hipError_t fit_loss_stop_f64(const double* partial, int64_t count, double* hist, int t,
+                             double tol, double conv, int W, int* stop, hipStream_t s) {
+    hipLaunchKernelGGL(fit_loss_stop_kernel<double>, dim3(1), dim3(kBlock), 0, s, partial, count,
+                       hist, t, tol, conv, W, stop);
     return hipGetLastError();
 }
 
@@ -828,6 +956,34 @@ hipError_t fit_theta(int P, const float* lb, const float* rng, const float* u, i
     }
     hipLaunchKernelGGL(fit_theta_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, tm, u, n, out);
+    return hipGetLastError();
+}
+
+// theta = lb + (ub - lb) u from an FP64 iterate, rounded once to FP32
+struct ThetaMapF64 {
+    int P;
+    double lb[kMaxP], rng[kMaxP];
+};
+__global__ __launch_bounds__(kBlock) void fit_theta_f64_kernel(ThetaMapF64 tm,
+                                                              const double* __restrict__ u,
+                                                              int64_t n, float* __restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    for (int p = 0; p < tm.P; ++p)
+        out[(int64_t)p * n + v] = (float)(tm.lb[p] + tm.rng[p] * u[(int64_t)p * n + v]);
+}
+
+hipError_t fit_theta_f64(int P, const double* lb, const double* rng, const double* u, int64_t n,
+                         float* out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    ThetaMapF64 tm{};
+    tm.P = P;
+    for (int p = 0; p < P; ++p) {
+        tm.lb[p] = lb[p];
+        tm.rng[p] = rng[p];
+    }
+    hipLaunchKernelGGL(fit_theta_f64_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, tm, u, n, out);
     return hipGetLastError();
 }
 

@@ -93,6 +93,19 @@ struct FitJob {
     float* partial;          // [nblk of this job] block loss partials (step path)
     int64_t blk0;            // first block of this job in the launch
     AcqDev acq;
+    // FP64 instantiation of the step path (the deterministic test path): the
+    // same constants unrounded and the iterate, moments and loss partials in
+    // FP64 (data, weights, prior maps and the start map stay FP32 inputs)
+    double lbd[kMaxP], rngd[kMaxP], u0d[kMaxP];
+    double lrd, epsd, momentumd, rhod, omb1d, omb2d, omrhod;
+    double scale_datad, scale_tvd, scale_priord;
+    double c1d, c2d;
+    double* ud;
+    const double* u_ind;
+    double* u_outd;
+    double* md;
+    double* vd;
+    double* partiald;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -119,6 +132,15 @@ int mh_pick_variant(int kind, int M, int uniform);   // code passed to mh_chunk
 
 // fits (gc_fit.hip)
 hipError_t fit_init(const FitJob* jobs, const BlkMap* map, int nblk, hipStream_t s);
+// FP64 instantiations of the step path: init, one iteration, and the map
+// theta = lb + rng u from an FP64 iterate, rounded once to FP32
+hipError_t fit_init_f64(const FitJob* jobs, const BlkMap* map, int nblk, hipStream_t s);
+hipError_t fit_step_f64(int kind, const FitJob* jobs, const BlkMap* map, int nblk, int xcd_remap,
+                        hipStream_t s);
+hipError_t fit_loss_stop_f64(const double* partial, int64_t count, double* hist, int t, double tol,
+                             double conv, int W, int* stop, hipStream_t s);
+hipError_t fit_theta_f64(int P, const double* lb, const double* rng, const double* u, int64_t n,
+                         float* out, hipStream_t s);
 hipError_t fit_fused(int kind, int maxm, const FitJob* jobs, const BlkMap* map, int nblk,
                      hipStream_t s);
 hipError_t fit_step(int kind, const FitJob* jobs, const BlkMap* map, int nblk, int xcd_remap,

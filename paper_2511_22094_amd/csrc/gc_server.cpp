@@ -1044,6 +1044,8 @@ int gc_submit(gc_server* S, const gc_job* job, uint64_t* job_id) {
             GC_REQUIRE(h.t_start == 0 && !h.init_state && !h.final_state, GC_E_INVAL,
                        "checkpoint / resume (t_start, init_state, final_state) is a "
                        "gc_fit_askadam option, not a server job's");
+            GC_REQUIRE(h.precision == GC_PREC_FP32, GC_E_INVAL,
+                       "server fit jobs run in FP32 (the FP64 fit is gc_fit_askadam's)");
         } else {
             set_error("unknown job kind");
             return GC_E_INVAL;

@@ -23,7 +23,7 @@ def _acq(acq):
     return te, bval, bvec
 
 
-def forward_jac(model, acq, th):
+def forward_jac(model, acq, th, F=np.float32):
     """s [Meff, n] and the rows ds/dtheta_p [Meff, n] (a list over p), float32,
     for th [P, n] float32."""
     te, bval, bvec = _acq(acq)
@@ -109,7 +109,7 @@ def _iso_links(mask, dim):
     return np.stack(nb)
 
 
-def _tv_term(kind, u_p, n, pairs, links, graph):
+def _tv_term(kind, u_p, n, pairs, links, graph, F=np.float32):
     """TV value (FP64 sum) and its subgradient (float32) for one map u_p [n]."""
     if kind == "aniso":
         a, b = pairs
@@ -140,7 +140,7 @@ def _tv_term(kind, u_p, n, pairs, links, graph):
 
 def askadam(model, acq, mask, y, lb, ub, *, n_iter, loss=2, lr=0.01, optimizer="adam",
             beta1=0.9, beta2=0.999, eps=1e-8, momentum=0.9, rho=0.9, lam=0.0, tv_mask=0,
-            tv_dim=3, x0=None, tv_kind="aniso", graph=None):
+            tv_dim=3, x0=None, tv_kind="aniso", graph=None, dtype=np.float32):
     """y [Meff, nz, ny, nx] float32 grid data; L2 loss only (loss=2); returns
     maps [P, n] (float64 of the float32 iterate) and the loss history.
     TV forms: "aniso" (sum of |forward differences| over in-mask pairs),
@@ -148,6 +148,7 @@ def askadam(model, acq, mask, y, lb, ub, *, n_iter, loss=2, lr=0.01, optimizer="
     "graph" (per vertex, the sum over its CSR neighbours, graph=(rowptr, col)
     over the masked voxels in grid order)."""
     assert loss == 2
+    F = dtype
     sel = mask.astype(bool)
     yc = np.asarray(y, F)[:, sel]                  # [Meff, n]
     n = yc.shape[1]
@@ -182,7 +183,7 @@ def askadam(model, acq, mask, y, lb, ub, *, n_iter, loss=2, lr=0.01, optimizer="
 
     def data_part(lo, hi):
         th = lb32[:, None] + rg32[:, None] * u[:, lo:hi]
-        s, J = forward_jac(model, acq, th)
+        s, J = forward_jac(model, acq, th, F)
         r = yc[:, lo:hi] - s
         for p in range(P):
             g[p, lo:hi] = rg32[p] * (F(-2) * scale * np.sum(J[p] * r, axis=0, dtype=F))
@@ -196,7 +197,7 @@ def askadam(model, acq, mask, y, lb, ub, *, n_iter, loss=2, lr=0.01, optimizer="
             for p in range(P):
                 if not (tv_mask >> p) & 1:
                     continue
-                R, gp = _tv_term(tv_kind, u[p], n, pairs, links, graph)
+                R, gp = _tv_term(tv_kind, u[p], n, pairs, links, graph, F)
                 loss_t += lam / n * R
                 g[p] += scale_tv * gp
         hist.append(loss_t)

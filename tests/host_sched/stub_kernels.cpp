@@ -583,5 +583,20 @@ hipError_t sense_forward_op(const SenseDev&, const float2*, float2*, float2*, hi
 hipError_t sense_adjoint_op(const SenseDev&, const float2*, float2*, float2*, hipStream_t) {
     GC_UNUSED_LAUNCHER("sense_adjoint_op");
 }
+// the FP64 fit path is gc_fit_askadam's; server jobs are FP32
+hipError_t fit_init_f64(const FitJob*, const BlkMap*, int, hipStream_t) {
+    GC_UNUSED_LAUNCHER("fit_init_f64");
+}
+hipError_t fit_step_f64(int, const FitJob*, const BlkMap*, int, int, hipStream_t) {
+    GC_UNUSED_LAUNCHER("fit_step_f64");
+}
+hipError_t fit_loss_stop_f64(const double*, int64_t, double*, int, double, double, int, int*,
+                             hipStream_t) {
+    GC_UNUSED_LAUNCHER("fit_loss_stop_f64");
+}
+hipError_t fit_theta_f64(int, const double*, const double*, const double*, int64_t, float*,
+                         hipStream_t) {
+    GC_UNUSED_LAUNCHER("fit_theta_f64");
+}
 
 }  // namespace gc

@@ -1,8 +1,10 @@
 """The FP32 re-run of the fit (tests/fp32_emulation.py), whose spread against
 the oracle sets the GPU fits' tolerances, is the oracle's algorithm: one
 plain gradient step reproduces the oracle's data + TV gradient (all three TV
-forms) to FP32 accuracy, and fits without TV -- where nothing amplifies
-rounding -- stay within FP32 rounding of the oracle."""
+forms) to FP32 accuracy, fits without TV -- where nothing amplifies
+rounding -- stay within FP32 rounding of the oracle, and run in FP64 the
+same code reproduces the oracle's fits, with and without TV, to FP64
+rounding."""
 import numpy as np
 import pytest
 
@@ -46,3 +48,19 @@ def test_fit_without_tv_within_fp32_rounding(orc, model):
     err = np.abs(emu - ref["maps"][:, d.mask.astype(bool)]) / (d.ub - d.lb)[:, None]
     assert err.max() < 3e-5, err.max()
     np.testing.assert_allclose(hist, ref["loss"], rtol=1e-4)
+
+
+@pytest.mark.parametrize("tv", [None, "aniso", "graph"])
+def test_fp64_run_reproduces_the_oracle(orc, tv):
+    acq = synth.dwi_acq(np.random.default_rng(2), dirs_per_shell=8)
+    d = synth.make_draw("dwi2", (4, 5, 6), 2, 0.02, acq=acq, block=2)
+    y = _y(orc, d)
+    kw = dict(n_iter=60)
+    if tv:
+        kw.update(lam=1e-3, tv_mask=0b111, tv_dim=3, tv_kind=tv,
+                  graph=grid_graph(d.mask, 3) if tv == "graph" else None)
+    ref = orc.askadam("dwi2", d.acq, d.mask, y, d.lb, d.ub, **kw)
+    emu, hist = em.askadam("dwi2", d.acq, d.mask, y, d.lb, d.ub, dtype=np.float64, **kw)
+    err = np.abs(emu - ref["maps"][:, d.mask.astype(bool)]) / (d.ub - d.lb)[:, None]
+    assert err.max() < 1e-12, err.max()
+    np.testing.assert_allclose(hist, ref["loss"], rtol=1e-12)
