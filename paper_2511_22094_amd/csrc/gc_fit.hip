@@ -191,18 +191,21 @@ template <typename T> __device__ __forceinline__ T absr(T x) {
     else return fabs(x);
 }
 
-// Anisotropic grid TV at voxel v for one map up (iterate t-1): the pairs
+// Anisotropic grid TV at voxel v for one map (iterate t-1): the pairs
 // (v, forward neighbour) add |difference| to R; the subgradient collects the
 // pairs in which v takes part.  nb = (x-, x+, y-, y+, z-, z+), -1 = none.
-// Neighbour values are read unconditionally (a missing neighbour, index -1,
-// reads element 0 and is then ignored) so that all reads of a voxel are in
-// flight together instead of one conditional read waiting after another.
+// Split in two so that the neighbour values of every regularised map are in
+// flight together before any subgradient waits on them.  They are read
+// unconditionally (a missing neighbour, index -1, reads element 0 and is then
+// ignored) so that no read waits behind a branch on the one before.
 template <typename T = float>
-__device__ __forceinline__ T tv_aniso_at(const T* __restrict__ up, T uv, const int32_t (&nb)[6],
-                                         T& R) {
-    T un[6];
+__device__ __forceinline__ void tv_aniso_load(const T* __restrict__ up, const int32_t (&nb)[6],
+                                              T (&un)[6]) {
 #pragma unroll
     for (int d = 0; d < 6; ++d) un[d] = gload(up)[nb[d] >= 0 ? nb[d] : 0];
+}
+template <typename T = float>
+__device__ __forceinline__ T tv_aniso_sub(const T (&un)[6], T uv, const int32_t (&nb)[6], T& R) {
     T g = 0;
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
@@ -226,7 +229,7 @@ __device__ __forceinline__ T tv_aniso_at(const T* __restrict__ up, T uv, const i
 template <typename T = float>
 __device__ __forceinline__ T tv_iso_at(const T* __restrict__ up, T uv, const int32_t (&nb)[6],
                                        const int32_t (&dg)[3][3], T& R) {
-    // all neighbour values first (unconditional reads, see tv_aniso_at)
+    // all neighbour values first (unconditional reads, as for the anisotropic form)
     T uf[3], ubk[3], ud[3][3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -505,15 +508,28 @@ __global__ __launch_bounds__(kBlock) void fit_step_kernel(const FitJob* __restri
         }
         const YGlob yg{J.y, n, v, J.acq.M};
         contrib = data_grad<Mdl, 0, YGlob, R>(J, u, yg, w, gu);
-        if (J.tv_mask) {
+        if (J.tv_mask && J.tv_kind == 0) {
+            // every regularised map's neighbour values requested first, then
+            // the subgradients in map order (measured 1 % faster than one
+            // round trip per map; same operations in the same order)
+            R Rtv = 0;
+            R un[P][6];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if ((J.tv_mask >> p) & 1u) tv_aniso_load<R>(uin + (int64_t)p * n, nb, un[p]);
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if ((J.tv_mask >> p) & 1u)
+                    gu[p] += F::scale_tv(J) * tv_aniso_sub<R>(un[p], u[p], nb, Rtv);
+            contrib += F::scale_tv(J) * Rtv;
+        } else if (J.tv_mask) {
             R Rtv = 0;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!((J.tv_mask >> p) & 1u)) continue;
                 const R* up = uin + (int64_t)p * n;
                 R g;
-                if (J.tv_kind == 0) g = tv_aniso_at<R>(up, u[p], nb, Rtv);
-                else if (J.tv_kind == 1) g = tv_iso_at<R>(up, u[p], nb, dg, Rtv);
+                if (J.tv_kind == 1) g = tv_iso_at<R>(up, u[p], nb, dg, Rtv);
                 else g = tv_graph_at<R>(up, u[p], J.g_rowptr, J.g_col, v, Rtv);
                 gu[p] += F::scale_tv(J) * g;
             }
