@@ -72,24 +72,24 @@ MH_GRE3_MIX_CEILING = FLOP_PER_MH_STEP_GRE3 * 64 / MH_GRE3_ISSUE_CYCLES / 64.0  
 # taken on: when their sha256 differs, `traffic` is reported as null.
 MEASURED_TRAFFIC = {
     "mh_chunk_cfg4": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "56798b367dbf8c20894cc721d3e608f65bd43c97414c2db16454f91a0d6d54fb",
-        "read_bytes": 3767460959, "write_bytes": 1804631552,
+        "sha256": "e940415284938bb3ca7ccfce49c4755f64735f70842dd9abb579225963da8963",
+        "read_bytes": 3767460437, "write_bytes": 1804631552,
         "profile": "profiles/mh_chunk_gre3_240x240x180_ellipsoid_8chains.md"},
     "mh_chunk_cfg1": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "56798b367dbf8c20894cc721d3e608f65bd43c97414c2db16454f91a0d6d54fb",
-        "read_bytes": 1595957473, "write_bytes": 788529152,
+        "sha256": "e940415284938bb3ca7ccfce49c4755f64735f70842dd9abb579225963da8963",
+        "read_bytes": 1595957219, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
     "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "f09dbc8d6dc65ae300cef49345ecb5e3a56e7594c5c646eec5be09881e3face2",
-        "read_bytes": 126895011, "write_bytes": 15728640,
+        "sha256": "0ca59763274bb25f8874936b1b8f4aee33116c767e69732bbe295377952cd445",
+        "read_bytes": 126818314, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "c6eb6184481b65f8ef0677579638a635744edc1f5b434efb036391502897e4aa",
-        "read_bytes": 112251863, "write_bytes": 100663296,
+        "sha256": "add332d77c688c1a337052c7ca83d09f71576f49f30bfdfebd7f2eba4807425b",
+        "read_bytes": 112252934, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "c6eb6184481b65f8ef0677579638a635744edc1f5b434efb036391502897e4aa",
-        "read_bytes": 147692825, "write_bytes": 111472128,
+        "sha256": "add332d77c688c1a337052c7ca83d09f71576f49f30bfdfebd7f2eba4807425b",
+        "read_bytes": 146335493, "write_bytes": 111472117,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
