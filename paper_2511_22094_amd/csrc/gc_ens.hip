@@ -17,6 +17,7 @@
 // the same steps; only the log-likelihoods carry last-bit differences, and
 // those matter only for acceptance decisions within rounding of a tie.
 #include "gc_internal.hpp"
+#include "gc_timing.hpp"
 
 namespace gc {
 
@@ -314,10 +315,10 @@ static hipError_t ens_chunk_t(const MhJob* jobs, const BlkMap* map, int nblk, in
     const size_t lds = (size_t)vpb * walkers * (Mdl::P + 1) * sizeof(R);
     const size_t lds_y = align16(lds) + (size_t)vpb * meff * sizeof(float);
     if (meff > 0 && lds_y <= kEnsLdsData)
-        hipLaunchKernelGGL((ens_chunk_kernel<KIND, R, true>), dim3(nblk), dim3(kBlock), lds_y, s,
+        GC_LAUNCH((ens_chunk_kernel<KIND, R, true>), dim3(nblk), dim3(kBlock), lds_y, s,
                            jobs, map);
     else
-        hipLaunchKernelGGL((ens_chunk_kernel<KIND, R, false>), dim3(nblk), dim3(kBlock), lds, s,
+        GC_LAUNCH((ens_chunk_kernel<KIND, R, false>), dim3(nblk), dim3(kBlock), lds, s,
                            jobs, map);
     return hipGetLastError();
 }

@@ -12,6 +12,7 @@
 // The per-voxel operations are the same functions in the same order, so the
 // two shapes give bit-identical iterates.
 #include "gc_internal.hpp"
+#include "gc_timing.hpp"
 
 namespace gc {
 
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void fit_fused_kernel(const FitJob* __restr
 
 template <int KIND, int MAXM>
 static hipError_t fused_t(const FitJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((fit_fused_kernel<KIND, MAXM>), dim3(nblk), dim3(kBlock), 0, s, jobs, map);
+    GC_LAUNCH((fit_fused_kernel<KIND, MAXM>), dim3(nblk), dim3(kBlock), 0, s, jobs, map);
     return hipGetLastError();
 }
 template <int KIND, int A, int B, int C>
@@ -574,7 +575,7 @@ hipError_t fit_step(int kind, const FitJob* jobs, const BlkMap* map, int nblk, i
                     hipStream_t s) {
 #define GC_STEP(K)                                                                      \
     case K:                                                                             \
-        hipLaunchKernelGGL((fit_step_kernel<K, float>), dim3(nblk), dim3(kBlock), 0, s, jobs, \
+        GC_LAUNCH((fit_step_kernel<K, float>), dim3(nblk), dim3(kBlock), 0, s, jobs, \
                            map, nblk, xcd_remap);                                       \
         break;
     switch (kind) {
@@ -593,7 +594,7 @@ hipError_t fit_step_f64(int kind, const FitJob* jobs, const BlkMap* map, int nbl
                         hipStream_t s) {
 #define GC_STEP(K)                                                                      \
     case K:                                                                             \
-        hipLaunchKernelGGL((fit_step_kernel<K, double>), dim3(nblk), dim3(kBlock), 0, s, jobs, \
+        GC_LAUNCH((fit_step_kernel<K, double>), dim3(nblk), dim3(kBlock), 0, s, jobs, \
                            map, nblk, xcd_remap);                                       \
         break;
     switch (kind) {

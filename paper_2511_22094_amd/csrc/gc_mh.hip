@@ -5,6 +5,7 @@
 // in HBM for the next chunk.  The same kernels serve one job or many (the
 // block work-list maps blocks to jobs).
 #include "gc_internal.hpp"
+#include "gc_timing.hpp"
 
 namespace gc {
 
@@ -318,7 +319,7 @@ hipError_t mh_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, in
 
 template <int KIND, typename R, int MAXM, int EXACT = 0, int RECUR = kRecurRuntime>
 static hipError_t chunk_t(const MhJob* jobs, const BlkMap* map, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((mh_chunk_kernel<KIND, R, MAXM, EXACT, RECUR>), dim3(nblk), dim3(kBlock), 0,
+    GC_LAUNCH((mh_chunk_kernel<KIND, R, MAXM, EXACT, RECUR>), dim3(nblk), dim3(kBlock), 0,
                        s, jobs, map);
     return hipGetLastError();
 }
@@ -329,7 +330,7 @@ template <int KIND, typename R>
 static hipError_t chunk_mem_t(const MhJob* jobs, const BlkMap* map, int nblk, size_t lds,
                               hipStream_t s) {
     if (lds == 0) return chunk_t<KIND, R, 0>(jobs, map, nblk, s);
-    hipLaunchKernelGGL((mh_chunk_kernel<KIND, R, 0, 0, kRecurRuntime, true>), dim3(nblk),
+    GC_LAUNCH((mh_chunk_kernel<KIND, R, 0, 0, kRecurRuntime, true>), dim3(nblk),
                        dim3(kBlock), lds, s, jobs, map);
     return hipGetLastError();
 }

@@ -20,6 +20,7 @@
 // kSenseMaxN, z at least kSenseMinNz.
 #include "gc_fft.hpp"
 #include "gc_sense.hpp"
+#include "gc_timing.hpp"
 
 namespace gc {
 
@@ -372,7 +373,7 @@ hipError_t launch_y(const SenseDev& S, const float2* in, float2* buf, float2* ou
                     const int* stop, hipStream_t s) {
     using Geo = YGeo<LOGY>;
     const int nblk = S.E * S.Nc * (S.Nz / Geo::G);
-    hipLaunchKernelGGL((sense_ycols_kernel<LOGY, MODE>), dim3(nblk), dim3(Geo::THREADS),
+    GC_LAUNCH((sense_ycols_kernel<LOGY, MODE>), dim3(nblk), dim3(Geo::THREADS),
                        Geo::LDS * sizeof(float2), s, S, in, buf, out, partial, stop);
     return hipGetLastError();
 }
@@ -395,7 +396,7 @@ hipError_t launch_z(const SenseDev& S, const SenseOpt& O, const float2* img_in, 
                     const int* stop, int fwd, hipStream_t s) {
     using Geo = ZGeo<LOGZ>;
     const int nblk = S.E * S.Ny;
-    hipLaunchKernelGGL((sense_zrows_kernel<LOGZ, MODE>), dim3(nblk), dim3(Geo::THREADS),
+    GC_LAUNCH((sense_zrows_kernel<LOGZ, MODE>), dim3(nblk), dim3(Geo::THREADS),
                        Geo::LDS * sizeof(float2), s, S, O, img_in, img_out, m, v, buf, out,
                        partial, stop, fwd);
     return hipGetLastError();

@@ -86,27 +86,39 @@ hipEvent_t trace_ref(int* dev_out) {
 bool timing_on() { return g_on.load() != 0; }
 int timing_every() { const int k = g_on.load(); return k > 0 ? k : 1; }
 
+DispatchEvents& dispatch_events() {
+    thread_local DispatchEvents slot;
+    return slot;
+}
+
 void LaunchTimer::begin() {
     if (!timing_on()) return;
     if (count++ % timing_every() != 0) return;
     if (tracing() && !ref) ref = trace_ref(&dev);
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
-    (void)hipEventRecord(e, s);
-    pending = e;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    pending = a;
+    pending_stop = b;
+    dispatch_events() = DispatchEvents{a, b, false};
 }
 
 void LaunchTimer::end() {
     if (!pending) return;
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) {
+    DispatchEvents& de = dispatch_events();
+    if (de.start == pending && de.taken) {
+        ev.emplace_back(pending, pending_stop);
+    } else {
+        // the launch did not take the events (it failed before its dispatch):
+        // it stays untimed
         (void)hipEventDestroy(pending);
-        pending = nullptr;
-        return;
+        (void)hipEventDestroy(pending_stop);
     }
-    (void)hipEventRecord(e, s);
-    ev.emplace_back(pending, e);
-    pending = nullptr;
+    de = DispatchEvents{};
+    pending = pending_stop = nullptr;
 }
 
 void LaunchTimer::flush() {
@@ -137,7 +149,11 @@ LaunchTimer::~LaunchTimer() {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
-    if (pending) (void)hipEventDestroy(pending);
+    if (pending) {
+        (void)hipEventDestroy(pending);
+        (void)hipEventDestroy(pending_stop);
+        if (dispatch_events().start == pending) dispatch_events() = DispatchEvents{};
+    }
 }
 
 }  // namespace gc
