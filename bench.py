@@ -72,24 +72,24 @@ MH_GRE3_MIX_CEILING = FLOP_PER_MH_STEP_GRE3 * 64 / MH_GRE3_ISSUE_CYCLES / 64.0  
 # taken on: when their sha256 differs, `traffic` is reported as null.
 MEASURED_TRAFFIC = {
     "mh_chunk_cfg4": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "e940415284938bb3ca7ccfce49c4755f64735f70842dd9abb579225963da8963",
+        "sha256": "66f4a2900892e98eaa6e99e292bfacaeda529440ef85e3eb9745914a1839ef11",
         "read_bytes": 3767460437, "write_bytes": 1804631552,
         "profile": "profiles/mh_chunk_gre3_240x240x180_ellipsoid_8chains.md"},
     "mh_chunk_cfg1": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "e940415284938bb3ca7ccfce49c4755f64735f70842dd9abb579225963da8963",
-        "read_bytes": 1595957219, "write_bytes": 788529152,
+        "sha256": "66f4a2900892e98eaa6e99e292bfacaeda529440ef85e3eb9745914a1839ef11",
+        "read_bytes": 1595957296, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
     "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "0ca59763274bb25f8874936b1b8f4aee33116c767e69732bbe295377952cd445",
-        "read_bytes": 126818314, "write_bytes": 15728648,
+        "sha256": "84a0a9bf78c80019bd427f15c544a78e892721eda50c2e6fa6f9bb6c2f0eda25",
+        "read_bytes": 126831605, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "add332d77c688c1a337052c7ca83d09f71576f49f30bfdfebd7f2eba4807425b",
-        "read_bytes": 112252934, "write_bytes": 100663321,
+        "sha256": "a6960523b58008b30ed39e2c247f0f7b58129960b529a6c5b462daaa9dbe5f5c",
+        "read_bytes": 112251763, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "add332d77c688c1a337052c7ca83d09f71576f49f30bfdfebd7f2eba4807425b",
-        "read_bytes": 146335493, "write_bytes": 111472117,
+        "sha256": "a6960523b58008b30ed39e2c247f0f7b58129960b529a6c5b462daaa9dbe5f5c",
+        "read_bytes": 147735137, "write_bytes": 111472117,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
