@@ -368,10 +368,10 @@ int validate_graph(Scratch& sc, int64_t n, int64_t nnz, const int64_t* rowptr,
     return GC_OK;
 }
 
-int pack_graph(Scratch& sc, const gc_adam_hyper* h, int64_t n, int mem_kind,
-               const int64_t** rowptr, const int32_t** col) {
-    *rowptr = nullptr;
-    *col = nullptr;
+int pack_graph(Scratch& sc, const gc_adam_hyper* h, int64_t n, int mem_kind, FitJob* J) {
+    J->g_rowptr = nullptr;
+    J->g_col = nullptr;
+    J->g_nnz = 0;
     if (!(h->lambda > 0) || h->tv_mask == 0 || h->tv_kind != GC_TV_GRAPH) return GC_OK;
     GC_REQUIRE(h->graph_n == n, GC_E_INVAL,
                "graph_n (%lld) must equal the number of masked voxels (%lld)",
@@ -386,8 +386,9 @@ int pack_graph(Scratch& sc, const gc_adam_hyper* h, int64_t n, int mem_kind,
     if ((rc = validate_graph(sc, n, h->graph_nnz, (const int64_t*)drp, (const int32_t*)dcol,
                              sc.s)))
         return rc;
-    *rowptr = (const int64_t*)drp;
-    *col = (const int32_t*)dcol;
+    J->g_rowptr = (const int64_t*)drp;
+    J->g_col = (const int32_t*)dcol;
+    J->g_nnz = h->graph_nnz;
     return GC_OK;
 }
 
@@ -738,11 +739,7 @@ int gc_fit_askadam(const gc_model* model, const gc_volume* data, const uint8_t* 
     if ((rc = pack_prior(sc, model, hyper, pk, ds.mem_kind, &pmu, &psg))) return rc;
     J.mu = pmu;
     J.sigma = psg;
-    const int64_t* grp = nullptr;
-    const int32_t* gcol = nullptr;
-    if ((rc = pack_graph(sc, hyper, n, ds.mem_kind, &grp, &gcol))) return rc;
-    J.g_rowptr = grp;
-    J.g_col = gcol;
+    if ((rc = pack_graph(sc, hyper, n, ds.mem_kind, &J))) return rc;
     float *u0 = nullptr, *u1 = nullptr, *m = nullptr, *v = nullptr;
     const size_t np = (size_t)std::max<int64_t>(n, 1) * P;
     GC_TRY_HIP(sc.alloc_n(&u0, np));

@@ -290,6 +290,56 @@ __device__ __forceinline__ T tv_graph_at(const T* __restrict__ up, T uv,
     return g;
 }
 
+// Graph TV split like the anisotropic form: the column indices of v's first
+// kGraphNb neighbours are read once for all regularised maps (unconditionally,
+// clamped into the adjacency; entries past v's degree are ignored), then each
+// map's values at them, all in flight together; a vertex with more
+// neighbours takes the rest one by one.  Same pairs in the same order as
+// tv_graph_at.
+constexpr int kGraphNb = 6;
+struct GraphNb {
+    int64_t k0, k1;
+    int32_t c[kGraphNb];
+};
+__device__ __forceinline__ void graph_nb_load(const int64_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col, int64_t nnz,
+                                              int64_t v, GraphNb& gn) {
+    gn.k0 = gload(rowptr)[v];
+    gn.k1 = gload(rowptr)[v + 1];
+#pragma unroll
+    for (int j = 0; j < kGraphNb; ++j) {
+        const int64_t k = gn.k0 + j;
+        gn.c[j] = nnz > 0 ? gload(col)[k < nnz ? k : nnz - 1] : 0;
+    }
+}
+template <typename T = float>
+__device__ __forceinline__ void tv_graph_load(const T* __restrict__ up, const GraphNb& gn,
+                                              T (&un)[kGraphNb]) {
+#pragma unroll
+    for (int j = 0; j < kGraphNb; ++j) un[j] = gload(up)[gn.c[j]];
+}
+template <typename T = float>
+__device__ __forceinline__ T tv_graph_sub(const T (&un)[kGraphNb], T uv, const GraphNb& gn,
+                                          const T* __restrict__ up,
+                                          const int32_t* __restrict__ col, T& R) {
+    T g = 0;
+    const int64_t deg = gn.k1 - gn.k0;
+#pragma unroll
+    for (int j = 0; j < kGraphNb; ++j) {
+        if (j < deg) {
+            const T diff = uv - un[j];
+            R += absr(diff);
+            g += (T)2 * sgn(diff);
+        }
+    }
+    for (int64_t k = gn.k0 + kGraphNb; k < gn.k1; ++k) {
+        const T diff = uv - up[col[k]];
+        R += absr(diff);
+        g += (T)2 * sgn(diff);
+    }
+    return g;
+}
+
 // Prior term (Eq. 6) of one voxel: scale_prior |(theta - mu) / sigma| summed
 // over the parameters of prior_mask, added to the loss (returned) and its
 // subgradient in u units to gu.
@@ -523,16 +573,26 @@ __global__ __launch_bounds__(kBlock) void fit_step_kernel(const FitJob* __restri
                 if ((J.tv_mask >> p) & 1u)
                     gu[p] += F::scale_tv(J) * tv_aniso_sub<R>(un[p], u[p], nb, Rtv);
             contrib += F::scale_tv(J) * Rtv;
+        } else if (J.tv_mask && J.tv_kind == 2) {
+            R Rtv = 0;
+            GraphNb gn;
+            graph_nb_load(J.g_rowptr, J.g_col, J.g_nnz, v, gn);
+            R un[P][kGraphNb];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if ((J.tv_mask >> p) & 1u) tv_graph_load<R>(uin + (int64_t)p * n, gn, un[p]);
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if ((J.tv_mask >> p) & 1u)
+                    gu[p] += F::scale_tv(J) *
+                             tv_graph_sub<R>(un[p], u[p], gn, uin + (int64_t)p * n, J.g_col, Rtv);
+            contrib += F::scale_tv(J) * Rtv;
         } else if (J.tv_mask) {
             R Rtv = 0;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!((J.tv_mask >> p) & 1u)) continue;
-                const R* up = uin + (int64_t)p * n;
-                R g;
-                if (J.tv_kind == 1) g = tv_iso_at<R>(up, u[p], nb, dg, Rtv);
-                else g = tv_graph_at<R>(up, u[p], J.g_rowptr, J.g_col, v, Rtv);
-                gu[p] += F::scale_tv(J) * g;
+                gu[p] += F::scale_tv(J) * tv_iso_at<R>(uin + (int64_t)p * n, u[p], nb, dg, Rtv);
             }
             contrib += F::scale_tv(J) * Rtv;
         }

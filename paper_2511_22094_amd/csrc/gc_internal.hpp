@@ -66,6 +66,7 @@ struct FitJob {
     int tv_kind;             // 0 anisotropic grid, 1 isotropic grid, 2 graph
     const int64_t* g_rowptr; // graph TV: CSR offsets [n + 1] over compact voxels
     const int32_t* g_col;    // graph TV: neighbour compact indices
+    int64_t g_nnz;           // graph TV: number of entries of g_col
     uint32_t prior_mask;     // prior (Eq. 6) on these parameters
     float scale_prior;       // prior_lambda / N
     const float* mu;         // [P][n] prior means (compacted) or nullptr

@@ -139,9 +139,9 @@ int pack_problem(Scratch& sc, const gc_model* m, const gc_volume* data, const ui
 int pack_prior(Scratch& sc, const gc_model* m, const gc_adam_hyper* h, const Packed& pk,
                int mem_kind, float** mu, float** sigma);
 // Graph adjacency of a fit with graph TV, in device memory and checked
-// (GC_E_INVAL unless it is a valid CSR over the n masked voxels).
-int pack_graph(Scratch& sc, const gc_adam_hyper* h, int64_t n, int mem_kind,
-               const int64_t** rowptr, const int32_t** col);
+// (GC_E_INVAL unless it is a valid CSR over the n masked voxels): sets the
+// descriptor's g_rowptr, g_col and g_nnz (null and 0 without graph TV).
+int pack_graph(Scratch& sc, const gc_adam_hyper* h, int64_t n, int mem_kind, FitJob* J);
 int validate_graph(Scratch& sc, int64_t n, int64_t nnz, const int64_t* rowptr,
                    const int32_t* col, hipStream_t s);
 

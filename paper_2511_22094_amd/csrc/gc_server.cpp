@@ -254,11 +254,7 @@ static int prepare_job(gc_server* S, Job* J) {
         if ((rc = pack_prior(sc, m, &h, J->pk, GC_MEM_HOST, &pmu, &psg))) return rc;
         q.mu = pmu;
         q.sigma = psg;
-        const int64_t* grp = nullptr;
-        const int32_t* gcol = nullptr;
-        if ((rc = pack_graph(sc, &h, n, GC_MEM_HOST, &grp, &gcol))) return rc;
-        q.g_rowptr = grp;
-        q.g_col = gcol;
+        if ((rc = pack_graph(sc, &h, n, GC_MEM_HOST, &q))) return rc;
         const size_t np = (size_t)std::max<int64_t>(n, 1) * P;
         GC_TRY_HIP(sc.alloc_n(&J->u0, np));
         GC_TRY_HIP(sc.alloc_n(&J->u1, np));

@@ -153,6 +153,8 @@ int main(int argc, char** argv) {
     std::vector<int32_t> acc(amax);
     std::vector<std::vector<uint8_t>> masks(trace.size());
     std::vector<gc_fit_report> reps(trace.size());
+    std::vector<std::vector<int64_t>> g_rowptr(trace.size());
+    std::vector<std::vector<int32_t>> g_col(trace.size());
 
     gc_server_cfg cfg{};
     cfg.device = 0;
@@ -206,6 +208,24 @@ int main(int argc, char** argv) {
                 job.adam.lambda = 1e-3;
                 job.adam.tv_mask = 0x7;
                 job.adam.tv_dim = 3;
+                if (i % 4 == 2) {
+                    // graph TV over the compacted voxels (the first n_vox of
+                    // a 64-wide grid): neighbours one and one row apart
+                    const int64_t n = j.n_vox;
+                    std::vector<int64_t>& rp = g_rowptr[i];
+                    std::vector<int32_t>& cl = g_col[i];
+                    rp.assign(1, 0);
+                    for (int64_t v = 0; v < n; ++v) {
+                        for (int64_t w : {v - 64, v - 1, v + 1, v + 64})
+                            if (w >= 0 && w < n) cl.push_back((int32_t)w);
+                        rp.push_back((int64_t)cl.size());
+                    }
+                    job.adam.tv_kind = GC_TV_GRAPH;
+                    job.adam.graph_n = n;
+                    job.adam.graph_rowptr = rp.data();
+                    job.adam.graph_col = cl.data();
+                    job.adam.graph_nnz = (int64_t)cl.size();
+                }
             }
             if (i % 5 == 1) {   // stopping rules: per-iteration launches with loss reductions
                 job.adam.tol = 1e-12;

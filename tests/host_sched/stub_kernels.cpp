@@ -347,6 +347,10 @@ hipError_t fit_step(int kind, const FitJob* jobs, const BlkMap* map, int nblk, i
                     int64_t nnz = 0;
                     if (dev_ok(J.g_rowptr, J.g_rowptr, (size_t)(J.n + 1) * 8, seq, k, "graph offsets"))
                         std::memcpy(&nnz, J.g_rowptr + J.n, 8);
+                    // the kernel clamps its column reads with the descriptor's count
+                    if (J.g_nnz != nnz)
+                        violation("%s: descriptor graph count %lld, offsets end at %lld", k,
+                                  (long long)J.g_nnz, (long long)nnz);
                     if (nnz > 0) dev_ok(J.g_col, J.g_col, (size_t)nnz * 4, seq, k, "graph columns");
                 }
             }
