@@ -72,24 +72,24 @@ MH_GRE3_MIX_CEILING = FLOP_PER_MH_STEP_GRE3 * 64 / MH_GRE3_ISSUE_CYCLES / 64.0  
 # taken on: when their sha256 differs, `traffic` is reported as null.
 MEASURED_TRAFFIC = {
     "mh_chunk_cfg4": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "66f4a2900892e98eaa6e99e292bfacaeda529440ef85e3eb9745914a1839ef11",
-        "read_bytes": 3767460437, "write_bytes": 1804631552,
+        "sha256": "686a21c629dceda2f3c737cef858ee887479bc9906bc6d6a96f95d67cce21686",
+        "read_bytes": 3767451139, "write_bytes": 1804631552,
         "profile": "profiles/mh_chunk_gre3_240x240x180_ellipsoid_8chains.md"},
     "mh_chunk_cfg1": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "66f4a2900892e98eaa6e99e292bfacaeda529440ef85e3eb9745914a1839ef11",
-        "read_bytes": 1595957296, "write_bytes": 788529152,
+        "sha256": "686a21c629dceda2f3c737cef858ee887479bc9906bc6d6a96f95d67cce21686",
+        "read_bytes": 1595953340, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
     "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "84a0a9bf78c80019bd427f15c544a78e892721eda50c2e6fa6f9bb6c2f0eda25",
-        "read_bytes": 126831605, "write_bytes": 15728648,
+        "sha256": "ba47f0f100714d24c789cf22f242973e60b8042d54c4d36620db598826eb5b81",
+        "read_bytes": 126822145, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "a6960523b58008b30ed39e2c247f0f7b58129960b529a6c5b462daaa9dbe5f5c",
-        "read_bytes": 112251763, "write_bytes": 100663321,
+        "sha256": "37825ba3c800f304ff3752e77ffd9c9a2fbf341626b7f8f8ef3e4e5c3c454b02",
+        "read_bytes": 112253244, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "a6960523b58008b30ed39e2c247f0f7b58129960b529a6c5b462daaa9dbe5f5c",
-        "read_bytes": 147735137, "write_bytes": 111472117,
+        "sha256": "37825ba3c800f304ff3752e77ffd9c9a2fbf341626b7f8f8ef3e4e5c3c454b02",
+        "read_bytes": 147202862, "write_bytes": 111472116,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
