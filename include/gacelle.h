@@ -429,13 +429,14 @@ int gc_philox_uniform_normal(uint64_t seed, const uint32_t *ctr, int64_t n, int 
                              void *out_u, void *out_z, const gc_exec *exec);
 
 /* ------------------------------------------------------------------------
- * Kernel timing (profiling aid).  While enabled, launches of a hot kernel
- * family are bracketed by HIP events recorded on the stream they run on;
+ * Kernel timing (profiling aid).  While enabled, a timed launch of a hot
+ * kernel family carries a pair of HIP events on its dispatch
+ * (hipExtLaunchKernelGGL), so the time is the kernel's own execution;
  * totals accumulate per family: "mh_chunk", "ens_chunk", "fit_fused",
  * "fit_step", and the two reconstruction passes "sense_ycols" and
  * "sense_zrows".  on = 0 disables (the default); on = k > 0 times every k-th
  * launch of a family within one call (k = 1: every launch), which bounds
- * the cost of the two event records per timed launch for families launched
+ * the host cost of the event pair per timed launch for families launched
  * once per iteration.  The count returned by gc_timing_get is that of the
  * timed launches.  Server rounds are read out when the round completes.
  *
@@ -446,8 +447,8 @@ int gc_philox_uniform_normal(uint64_t seed, const uint32_t *ctr, int64_t n, int 
  * ({"traceEvents": [{"name", "ph": "X", "pid": device, "tid": stream,
  * "ts", "dur"} ...]}, microseconds).  Start times count from a reference
  * event recorded once per device, after a device synchronisation, when its
- * first traced launch begins.  The two event records per launch cost a few
- * microseconds each: tracing is a profiling mode, not for timing runs.
+ * first traced launch begins.  Creating and reading the event pair of every
+ * launch costs host time: tracing is a profiling mode, not for timing runs.
  * ------------------------------------------------------------------------ */
 int gc_timing_enable(int on);
 /* Total event time (ms) and launch count of a family since the last reset. */
