@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from gpu_util import G, say
-from graphs import grid_graph
+from graphs import grid_graph, random_graph
 from paper_2511_22094_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -83,19 +83,29 @@ def test_fp64_fits_follow_the_oracle(orc, model, opt):
     np.testing.assert_allclose(out["loss"], ref["loss"], rtol=1e-11)
 
 
-@pytest.mark.parametrize("kind", ["aniso", "iso", "graph"])
+@pytest.mark.parametrize("kind", ["aniso", "iso", "graph", "graph_dense"])
 def test_fp64_tv_fits_follow_the_oracle(orc, kind):
     """The anisotropic and graph forms agree to the FP32 rounding of the
     maps.  The isotropic form divides by the local gradient norm, which is
     near 0 on the flat blocks of these maps: there even FP64 rounding-order
     differences grow (an FP64 re-run of the algorithm parts from the oracle
-    by up to ~4e-4 of the range), and the GPU is held to that spread."""
+    by up to ~4e-4 of the range), and the GPU is held to that spread.
+    graph_dense: a random symmetric adjacency whose vertices have 3 to 12
+    neighbours (a third of them more than six), so the step kernel takes both
+    its first-six read and the one-by-one remainder."""
     import fp32_emulation as em
     acq = synth.dwi_acq(np.random.default_rng(2), dirs_per_shell=8)
     d = synth.make_draw("dwi2", (6, 8, 10), 2, 0.02, acq=acq, block=4)
     yg = _inputs(orc, d)
     m = G().Model.from_acq("dwi2", d.acq)
-    graph = grid_graph(d.mask, 3) if kind == "graph" else None
+    graph = None
+    if kind == "graph":
+        graph = grid_graph(d.mask, 3)
+    elif kind == "graph_dense":
+        graph = random_graph(d.n, 3, 31)
+        deg = np.diff(graph[0])
+        assert deg.min() <= 6 < deg.max()
+        kind = "graph"
     out = G().gc_fit_askadam(m, yg, d.mask, d.lb, d.ub, n_iter=100, lam=1e-3,
                              tv_params=(0, 1, 2), tv_dim=3, tv_kind=kind, graph=graph,
                              precision="fp64", loss_history=True)

@@ -99,7 +99,7 @@ def _draw_with_start(orc, shape, seed):
     return d, yg, x0
 
 
-@pytest.mark.parametrize("reg", ["iso", "iso2d", "graph", "prior", "prior+iso"])
+@pytest.mark.parametrize("reg", ["iso", "iso2d", "graph", "graph_dense", "prior", "prior+iso"])
 def test_regulariser_gradient_in_fit_matches_oracle(orc, reg):
     d, yg, x0 = _draw_with_start(orc, (4, 6, 7), 21)
     kg, ko = {}, {}
@@ -107,8 +107,10 @@ def test_regulariser_gradient_in_fit_matches_oracle(orc, reg):
         dim = 2 if reg == "iso2d" else 3
         kg.update(lam=0.05, tv_params=(0, 1, 2), tv_dim=dim, tv_kind="iso")
         ko.update(lam=0.05, tv_mask=0b111, tv_dim=dim, tv_kind="iso")
-    if reg == "graph":
-        gr = grid_graph(d.mask, 3)
+    if reg.startswith("graph"):
+        # graph_dense: vertices of more than six neighbours take the step
+        # kernel's one-by-one remainder after its first-six read
+        gr = grid_graph(d.mask, 3) if reg == "graph" else random_graph(d.n, 3, 33)
         kg.update(lam=0.05, tv_params=(0, 1, 2), tv_kind="graph", graph=gr)
         ko.update(lam=0.05, tv_mask=0b111, tv_kind="graph", graph=gr)
     if "prior" in reg:
