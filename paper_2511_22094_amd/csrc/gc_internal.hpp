@@ -115,7 +115,8 @@ hipError_t mh_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, in
                    hipStream_t s);
 // chains > 0: every job of the launch has that many chains, and instantiations
 // that read their data from memory then share it through LDS among the chains
-// of a voxel (when kBlock / chains * meff floats fit in kMhSharedData bytes);
+// of a voxel (when kBlock / chains rows of (meff | 1) floats fit in
+// kMhSharedData bytes);
 // meff = the jobs' effective measurement count (M, or 2 M if complex)
 constexpr size_t kMhSharedData = 48 * 1024;
 hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkMap* map,

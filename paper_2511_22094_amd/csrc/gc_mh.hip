@@ -145,19 +145,24 @@ __global__ __launch_bounds__(kBlock) void mh_chunk_kernel(const MhJob* __restric
     int c;
     YShared ys{nullptr, J.acq.M};
     if constexpr (SHARED) {
-        extern __shared__ float ysm[];   // [kBlock / C][Meff]
+        // [kBlock / C][Ms]: a voxel's Meff values, rows padded to an odd
+        // length Ms so that the voxels a wave reads at one measurement index
+        // fall in different LDS banks (an even row of 96 floats put all of
+        // them in one bank)
+        extern __shared__ float ysm[];
         const int C = J.C, vb = kBlock / C, Me = CPLX ? 2 * J.acq.M : J.acq.M;
+        const int Ms = Me | 1;
         const int64_t v0 = bm.lane0 / C;
         for (int idx = threadIdx.x; idx < vb * Me; idx += kBlock) {
             const int j = idx / vb, a = idx % vb;   // row j, voxel v0 + a: coalesced
-            ysm[a * Me + j] = v0 + a < n ? gload(J.y)[(int64_t)j * n + v0 + a] : 0.f;
+            ysm[a * Ms + j] = v0 + a < n ? gload(J.y)[(int64_t)j * n + v0 + a] : 0.f;
         }
         __syncthreads();
         v = v0 + threadIdx.x / C;
         c = (int)(threadIdx.x % C);
         if (v >= n) return;
         L = (int64_t)c * n + v;
-        ys.p = ysm + (threadIdx.x / C) * Me;
+        ys.p = ysm + (threadIdx.x / C) * Ms;
     } else {
         L = bm.lane0 + threadIdx.x;
         if (L >= NL) return;
@@ -356,9 +361,12 @@ static hipError_t chunk_f32(int variant, const MhJob* jobs, const BlkMap* map, i
 
 hipError_t mh_chunk(int kind, bool fp64, int maxm, const MhJob* jobs, const BlkMap* map,
                     int nblk, int chains, int meff, hipStream_t s) {
+    // rows padded to an odd length, as the kernel lays them out (meff is at
+    // least every job's own count, so meff | 1 covers each job's padded row)
+    const size_t row = (size_t)(meff | 1) * sizeof(float);
     const bool share = chains > 0 && kBlock % chains == 0 && meff > 0 &&
-                       (size_t)(kBlock / chains) * meff * sizeof(float) <= kMhSharedData;
-    const size_t lds = share ? (size_t)(kBlock / chains) * meff * sizeof(float) : 0;
+                       (size_t)(kBlock / chains) * row <= kMhSharedData;
+    const size_t lds = share ? (size_t)(kBlock / chains) * row : 0;
     if (fp64) {
         switch (kind) {
             case MONOEXP_T2S: return chunk_mem_t<MONOEXP_T2S, double>(jobs, map, nblk, lds, s);
