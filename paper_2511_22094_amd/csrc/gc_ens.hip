@@ -56,6 +56,12 @@ template <bool CPLX> struct YLdsE {
 
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
 
+// Staged row length for Me floats: odd for real data; for (re, im) pairs an
+// odd number of pairs, so pairs stay 8-byte aligned.
+__host__ __device__ constexpr int ens_row(int Me, bool cplx) {
+    return cplx ? ((Me / 2) % 2 == 0 ? Me + 2 : Me) : (Me | 1);
+}
+
 __device__ __forceinline__ int first_keep_e(int t0, int burnin, int thin) {
     int t = t0 > burnin ? t0 : burnin;
     int r = (t - burnin + 1) % thin;
@@ -148,8 +154,11 @@ __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restri
     R* LP = X + (size_t)vpb * K * P;     // [vpb][K]
     R* TH = (R*)J.th;
     R* LLg = (R*)J.ll;
-    // [vpb][Me] measurements (Me = M, or 2 M as (re, im) pairs), after the walkers
+    // [vpb][Ms] measurements (Me = M, or 2 M as (re, im) pairs), after the
+    // walkers; rows padded to Ms so that the voxels a wave reads at one index
+    // fall in different LDS banks
     const int Me = CPLX ? 2 * J.acq.M : J.acq.M;
+    const int Ms = ens_row(Me, CPLX);
     float* Yl = (float*)(smem + align16((size_t)vpb * K * (P + 1) * sizeof(R)));
     if constexpr (YLDS) {
         // consecutive threads take consecutive voxels of one row: coalesced reads
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restri
             const int j = idx / vpb, a = idx % vpb;
             const int64_t va = bm.lane0 + a;
             const int row = CPLX ? ((j & 1) ? J.acq.M + (j >> 1) : (j >> 1)) : j;
-            Yl[a * Me + j] = va < n ? gload(J.y)[(int64_t)row * n + va] : 0.f;
+            Yl[a * Ms + j] = va < n ? gload(J.y)[(int64_t)row * n + va] : 0.f;
         }
     }
     // load the ensemble of every voxel of the block
@@ -224,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void ens_chunk_kernel(const MhJob* __restri
 #pragma unroll
                 for (int p = 0; p < P; ++p) ev[p] = inb ? Y[p] : Xv[(size_t)k * P + p];
                 if constexpr (YLDS)
-                    llp = nscale * Mdl::template sse<0>(ev, YLdsE<CPLX>{Yl + vl * Me}, J.acq);
+                    llp = nscale * Mdl::template sse<0>(ev, YLdsE<CPLX>{Yl + vl * Ms}, J.acq);
                 else
                     llp = nscale * Mdl::template sse<0>(ev, y, J.acq);
                 const R lhs = Math<R>::ln(uniform01<R>(o.z));
@@ -305,7 +314,8 @@ hipError_t ens_init(int kind, bool fp64, const MhJob* jobs, const BlkMap* map, i
 // Launch for jobs whose walker count is `walkers` (the map covers voxels in
 // groups of kBlock / (walkers / 2)) and whose effective measurement counts are
 // at most `meff`; dynamic LDS = vpb * K * (P + 1) reals for the walkers, plus
-// vpb * meff floats of staged data when that fits in kEnsLdsData bytes.
+// vpb rows of staged data (meff floats, padded: ens_row) when that fits in
+// kEnsLdsData bytes.
 constexpr size_t kEnsLdsData = 64 * 1024;
 template <int KIND, typename R>
 static hipError_t ens_chunk_t(const MhJob* jobs, const BlkMap* map, int nblk, int walkers,
@@ -313,7 +323,8 @@ static hipError_t ens_chunk_t(const MhJob* jobs, const BlkMap* map, int nblk, in
     using Mdl = typename ModelOf<KIND, R>::T;
     const int hp = walkers / 2, vpb = kBlock / hp;
     const size_t lds = (size_t)vpb * walkers * (Mdl::P + 1) * sizeof(R);
-    const size_t lds_y = align16(lds) + (size_t)vpb * meff * sizeof(float);
+    // meff is at least every job's own count, so its padded row covers theirs
+    const size_t lds_y = align16(lds) + (size_t)vpb * ens_row(meff, Mdl::kComplex) * sizeof(float);
     if (meff > 0 && lds_y <= kEnsLdsData)
         GC_LAUNCH((ens_chunk_kernel<KIND, R, true>), dim3(nblk), dim3(kBlock), lds_y, s,
                            jobs, map);
