@@ -72,24 +72,24 @@ MH_GRE3_MIX_CEILING = FLOP_PER_MH_STEP_GRE3 * 64 / MH_GRE3_ISSUE_CYCLES / 64.0  
 # taken on: when their sha256 differs, `traffic` is reported as null.
 MEASURED_TRAFFIC = {
     "mh_chunk_cfg4": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "686a21c629dceda2f3c737cef858ee887479bc9906bc6d6a96f95d67cce21686",
-        "read_bytes": 3767451139, "write_bytes": 1804631552,
+        "sha256": "5074f0a9ea404a17994d77f714cefdd61a55eabcd18e5453ab1a070fe0039569",
+        "read_bytes": 3767453787, "write_bytes": 1804631552,
         "profile": "profiles/mh_chunk_gre3_240x240x180_ellipsoid_8chains.md"},
     "mh_chunk_cfg1": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "686a21c629dceda2f3c737cef858ee887479bc9906bc6d6a96f95d67cce21686",
-        "read_bytes": 1595953340, "write_bytes": 788529152,
+        "sha256": "5074f0a9ea404a17994d77f714cefdd61a55eabcd18e5453ab1a070fe0039569",
+        "read_bytes": 1595954429, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
     "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "ba47f0f100714d24c789cf22f242973e60b8042d54c4d36620db598826eb5b81",
-        "read_bytes": 126822145, "write_bytes": 15728648,
+        "sha256": "8c3ae8dc745bbfc5000501a9042f99b2fd2a3150ab1de42f0015233d38d2d265",
+        "read_bytes": 126927870, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "37825ba3c800f304ff3752e77ffd9c9a2fbf341626b7f8f8ef3e4e5c3c454b02",
-        "read_bytes": 112253244, "write_bytes": 100663321,
+        "sha256": "56374230962df4effbbbd43c0318bef4b45b73fc5bf26601d6cda4f20a94b89f",
+        "read_bytes": 112251802, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "37825ba3c800f304ff3752e77ffd9c9a2fbf341626b7f8f8ef3e4e5c3c454b02",
-        "read_bytes": 147202862, "write_bytes": 111472116,
+        "sha256": "56374230962df4effbbbd43c0318bef4b45b73fc5bf26601d6cda4f20a94b89f",
+        "read_bytes": 147755180, "write_bytes": 111472118,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 
