@@ -174,6 +174,7 @@ def mh_leg(g, torch, steps, warmup, which="cfg4", sample=None):
     t1 = time.perf_counter()
     g.gc_timing_enable(False)
     kms, nl = g.gc_timing_get("mh_chunk")
+    gms, gnl = g.gc_timing_get("gather_rows")
     n = d.n
     units = n * kw["n_chains"] * kw["n_iter"]
     sec = (t1 - t0) / steps
@@ -189,9 +190,20 @@ def mh_leg(g, torch, steps, warmup, which="cfg4", sample=None):
                    std.reshape(9, -1)[:, sidx].cpu().numpy())
     del y, mean, std
     torch.cuda.empty_cache()
+    # the pack step's gather (a1): Meff rows of n masked voxels read and written,
+    # plus the n-entry index
+    gather = None
+    if gnl > 0:
+        gbytes = 2 * m.n_meas_eff * n * 4 + n * 4
+        gus = gms * 1e3 / gnl
+        gather = {"bound": "hbm", "kernel": "gather_rows", "launch_us": gus,
+                  "bytes_per_launch": gbytes, "achieved": gbytes / (gus * 1e-6) / 1e9,
+                  "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": gbytes / (gus * 1e-6) / 1e9 / PEAK_HBM_GBS}
     return dict(units=units, sec=sec, value=units / sec, per_launch_ms=per_launch_s * 1e3,
                 launches=launches_per_step, units_per_launch=units_per_launch,
-                achieved_tflops=achieved, finite=finite, n=n, moments=moments, kw=kw)
+                achieved_tflops=achieved, finite=finite, n=n, moments=moments, kw=kw,
+                gather=gather)
 
 
 def adam_leg(g, torch, steps, warmup):
@@ -1046,6 +1058,7 @@ def main():
                                          MH_GRE3_MIX_CEILING),
                      "steps_per_launch": mh["units_per_launch"],
                      "launch_ms": mh["per_launch_ms"]},
+        "pack": mh["gather"],
         "cpu_baseline": cpu,
         "speedup_vs_cpu_oracle": (mh["value"] / cpu["value"]) if cpu else None,
         "paper_context": paper_context(mh, cpu, adam, adam_err),

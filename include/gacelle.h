@@ -433,8 +433,9 @@ int gc_philox_uniform_normal(uint64_t seed, const uint32_t *ctr, int64_t n, int 
  * kernel family carries a pair of HIP events on its dispatch
  * (hipExtLaunchKernelGGL), so the time is the kernel's own execution;
  * totals accumulate per family: "mh_chunk", "ens_chunk", "fit_fused",
- * "fit_step", and the two reconstruction passes "sense_ycols" and
- * "sense_zrows".  on = 0 disables (the default); on = k > 0 times every k-th
+ * "fit_step", the two reconstruction passes "sense_ycols" and
+ * "sense_zrows", and "gather_rows" (the pack step's gather of the measured
+ * data into compacted rows).  on = 0 disables (the default); on = k > 0 times every k-th
  * launch of a family within one call (k = 1: every launch), which bounds
  * the host cost of the event pair per timed launch for families launched
  * once per iteration.  The count returned by gc_timing_get is that of the

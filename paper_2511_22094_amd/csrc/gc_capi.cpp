@@ -306,7 +306,18 @@ int pack_problem(Scratch& sc, const gc_model* m, const gc_volume* data, const ui
     GC_TRY_HIP(sc.alloc_n(&flag, 1));
     GC_TRY_HIP(fill_i32(flag, 1, 0, s));
     GC_TRY_HIP(sc.alloc_n(&out->y, (size_t)std::max<int64_t>(n, 1) * m->Meff));
-    GC_TRY_HIP(gather_rows((const float*)dy, m->Meff, G, plan.c2g, n, out->y, flag, s));
+    {
+        // the pack step's data gather; timed like the hot kernels, except on
+        // the allocation-free path (whose scratch is fixed), as there
+        LaunchTimer tm("gather_rows", s);
+        if (!sc.fixed) tm.begin();
+        GC_TRY_HIP(gather_rows((const float*)dy, m->Meff, G, plan.c2g, n, out->y, flag, s));
+        tm.end();
+        if (!tm.ev.empty()) {   // timed: read it out here (a profiling mode)
+            GC_TRY_HIP(hipStreamSynchronize(s));
+            tm.flush();
+        }
+    }
     out->w = nullptr;
     if (dw) {
         GC_TRY_HIP(sc.alloc_n(&out->w, (size_t)std::max<int64_t>(n, 1)));

@@ -3,6 +3,7 @@
 // neighbour tables for the TV stencil, deterministic reductions, and the
 // random-stream test kernels.
 #include "gc_internal.hpp"
+#include "gc_timing.hpp"
 
 namespace gc {
 
@@ -106,40 +107,73 @@ hipError_t pack_index(const uint8_t* mask, PackPlan& plan, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ gathers
+// A thread reads its voxel's index once and moves kRowsPer rows of it, the
+// reads all in flight before the writes (one row per thread re-read the
+// index for every row and had one read in flight).
+constexpr int kRowsPer = 8;
+
 // dst[r][c] = src[r][c2g[c]] for r < rows; flags non-finite values.
 __global__ __launch_bounds__(kBlock) void gather_rows_kernel(const float* __restrict__ src,
                                                             int64_t n_grid,
                                                             const int32_t* __restrict__ c2g,
-                                                            int64_t n, float* __restrict__ dst,
+                                                            int64_t n, int64_t rows,
+                                                            float* __restrict__ dst,
                                                             int* __restrict__ flag) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t r = blockIdx.y;
     if (c >= n) return;
+    const int64_t r0 = (int64_t)blockIdx.y * kRowsPer;
     const int64_t a = c2g ? (int64_t)c2g[c] : c;
-    const float x = src[r * n_grid + a];
-    dst[r * n + c] = x;
-    if (flag && !isfinite(x)) atomicOr(flag, 1);
+    float x[kRowsPer];
+#pragma unroll
+    for (int k = 0; k < kRowsPer; ++k) {
+        // rows past the end re-read the last row (unconditional reads); not stored
+        const int64_t r = r0 + k < rows ? r0 + k : rows - 1;
+        x[k] = src[r * n_grid + a];
+    }
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kRowsPer; ++k) {
+        if (r0 + k < rows) {
+            dst[(r0 + k) * n + c] = x[k];
+            bad |= !isfinite(x[k]);
+        }
+    }
+    if (flag && bad) atomicOr(flag, 1);
 }
 
 hipError_t gather_rows(const float* src, int64_t rows, int64_t n_grid, const int32_t* c2g,
                        int64_t n, float* dst, int* flag, hipStream_t s) {
     if (n == 0 || rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock), (unsigned)rows),
-                       dim3(kBlock), 0, s, src, n_grid, c2g, n, dst, flag);
+    GC_LAUNCH(gather_rows_kernel,
+              dim3((unsigned)((n + kBlock - 1) / kBlock), (unsigned)((rows + kRowsPer - 1) / kRowsPer)),
+              dim3(kBlock), 0, s, src, n_grid, c2g, n, rows, dst, flag);
     return hipGetLastError();
 }
 
-// dst[r][a] = g2c[a] >= 0 ? src[r][g2c[a]] : 0
+// dst[r][a] = g2c[a] >= 0 ? src[r][g2c[a]] : 0, kRowsPer rows per thread
 template <typename T>
 __global__ __launch_bounds__(kBlock) void scatter_rows_kernel(const T* __restrict__ src,
                                                              int64_t n,
                                                              const int32_t* __restrict__ g2c,
-                                                             int64_t n_grid, T* __restrict__ dst) {
+                                                             int64_t n_grid, int64_t rows,
+                                                             T* __restrict__ dst) {
     const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t r = blockIdx.y;
     if (a >= n_grid) return;
+    const int64_t r0 = (int64_t)blockIdx.y * kRowsPer;
     const int32_t c = g2c ? g2c[a] : (int32_t)a;
-    dst[r * n_grid + a] = c >= 0 ? src[r * n + c] : (T)0;
+    T x[kRowsPer];
+#pragma unroll
+    for (int k = 0; k < kRowsPer; ++k) x[k] = (T)0;
+    if (c >= 0) {   // voxels outside the mask read nothing (src may be empty)
+#pragma unroll
+        for (int k = 0; k < kRowsPer; ++k) {
+            const int64_t r = r0 + k < rows ? r0 + k : rows - 1;
+            x[k] = src[r * n + c];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kRowsPer; ++k)
+        if (r0 + k < rows) dst[(r0 + k) * n_grid + a] = x[k];
 }
 
 template <typename T>
@@ -147,8 +181,9 @@ static hipError_t scatter_t(const T* src, int64_t rows, int64_t n, const int32_t
                             int64_t n_grid, T* dst, hipStream_t s) {
     if (n_grid == 0 || rows == 0) return hipSuccess;
     hipLaunchKernelGGL((scatter_rows_kernel<T>),
-                       dim3((unsigned)((n_grid + kBlock - 1) / kBlock), (unsigned)rows),
-                       dim3(kBlock), 0, s, src, n, g2c, n_grid, dst);
+                       dim3((unsigned)((n_grid + kBlock - 1) / kBlock),
+                            (unsigned)((rows + kRowsPer - 1) / kRowsPer)),
+                       dim3(kBlock), 0, s, src, n, g2c, n_grid, rows, dst);
     return hipGetLastError();
 }
 hipError_t scatter_rows_f32(const float* src, int64_t rows, int64_t n, const int32_t* g2c,
