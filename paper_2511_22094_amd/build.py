@@ -37,7 +37,7 @@ def source_files():
 
 
 def source_hash() -> str:
-    """sha256 (first 16 hex digits) over the library's sources and this build
+    """sha256 (first 16 hex digits) over the library's sources and its build
     script; embedded in the library and returned by gc_version(), so a run can
     tell whether the library it loaded was built from the sources beside it."""
     root, files = source_files()
