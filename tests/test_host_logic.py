@@ -1,5 +1,6 @@
-"""Host-side helpers that need no GPU: the bench's mesh adjacency and the
-synthetic reconstruction inputs."""
+"""Host-side helpers that need no GPU: the bench's mesh adjacency, its
+paper-context ratios and traffic bookkeeping, and the synthetic
+reconstruction inputs."""
 import numpy as np
 
 from graphs import grid_graph
@@ -52,3 +53,34 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120, cwd=root)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_paper_context_ratios():
+    """The speed-ups over one oracle core are this build's GPU rates over the
+    single-thread oracle rates, set beside the paper's quoted figures."""
+    import bench
+    mh = {"value": 6.0e10}
+    cpu = {"value": 1.6e7, "single_thread": {"value": 1.0e6}}
+    adam = {"value": 9.0e9}
+    adam_err = {"cpu_oracle": {"single_thread": {"value": 6.0e5}}}
+    c = bench.paper_context(mh, cpu, adam, adam_err)
+    assert c["mh_gre3_vs_one_oracle_core"] == 6.0e4
+    assert c["adam_tv_dwi2_vs_one_oracle_core"] == 1.5e4
+    assert c["paper_mh_nexi_vs_one_cpu_core"] == 14380
+    assert c["paper_adam_nexi_vs_one_cpu_core"] == 451
+    # without the CPU baseline there is no ratio to give
+    assert bench.paper_context(mh, None, adam, adam_err) is None
+    assert "adam_tv_dwi2_vs_one_oracle_core" not in bench.paper_context(mh, cpu, None, None)
+
+
+def test_bench_measured_traffic_follows_the_kernel_sources(monkeypatch):
+    """Counter-based traffic is reported only for the sources it was taken
+    on: a different recorded hash gives null."""
+    import copy
+    import bench
+    table = copy.deepcopy(bench.MEASURED_TRAFFIC)
+    key = "fit_step"
+    table[key]["sha256"] = "0" * 64
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", table)
+    assert bench.measured_traffic(key) is None
+    assert bench.measured_traffic("no such kernel") is None
