@@ -474,7 +474,10 @@ typedef struct gc_server gc_server;
 typedef struct {
     int device;            /* HIP device ordinal */
     size_t hbm_budget;     /* bytes of device memory for resident jobs (0 = half free) */
-    int max_slots;         /* resident jobs at most (0 = 64) */
+    int max_slots;         /* resident jobs at most; 0 = 64, and beyond that up
+                              to 256 while the resident jobs hold fewer than
+                              2^21 voxel x chain lanes (many small jobs then
+                              share launches) */
     int chunk_iters;       /* MCMC iterations per shared launch (0 = 500) */
     int baseline;          /* 1 = one job at a time, synchronous copies, one job per
                               launch (the comparison path); 0 = batching */

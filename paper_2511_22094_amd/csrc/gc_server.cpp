@@ -61,6 +61,12 @@ struct PinnedPool {
     }
 };
 
+// Default admission: 64 resident jobs, or more (up to kMaxSlotsSmall) while
+// the resident jobs hold fewer than kFillLanes lanes (voxel x chain pairs),
+// about four rounds of waves of the whole GPU.
+constexpr int kMaxSlotsSmall = 256;
+constexpr int64_t kFillLanes = int64_t(1) << 21;
+
 struct Job {
     uint64_t id = 0;
     gc_job spec{};
@@ -72,6 +78,7 @@ struct Job {
     bool cancel = false;
     double t_submit = 0, t_done = 0;
     size_t footprint = 0;
+    int64_t lanes = 0;   // masked voxels x chains (walkers; 1 for a fit)
     int64_t G = 0, n = 0;
     // device residency
     std::unique_ptr<Scratch> mem;
@@ -126,6 +133,7 @@ struct gc_server {
     std::unordered_map<uint64_t, std::unique_ptr<gc::Job>> jobs;
     std::vector<gc::Job*> resident;
     size_t used = 0;
+    int64_t resident_lanes = 0;   // lanes of the resident jobs
     hipStream_t prep = nullptr, compute = nullptr, copy = nullptr;
     // launch lanes of a round (batched mode): the groups of a round run on
     // these streams side by side, fenced by `lane_start` (after the round's
@@ -798,6 +806,7 @@ static void complete_job(gc_server* S, Job* J, int status) {
         S->n_fail++;
     }
     S->used -= J->footprint;
+    S->resident_lanes -= J->lanes;
     S->resident.erase(std::remove(S->resident.begin(), S->resident.end(), J), S->resident.end());
     model_release(J->spec.model);   // the job's reference (taken at submission)
     J->spec.model = nullptr;
@@ -825,6 +834,10 @@ static void scheduler(gc_server* S) {
             S->wake.wait_for(lk, std::chrono::milliseconds(inflight.empty() && S->resident.empty() ? 50 : 0),
                              [&] { return S->stopping || !S->queue.empty() || !S->resident.empty(); });
             const int slots = S->cfg.baseline ? 1 : (S->cfg.max_slots > 0 ? S->cfg.max_slots : 64);
+            // default slots: beyond 64 (up to kMaxSlotsSmall) while the
+            // resident jobs' lanes are too few to fill the GPU, so that many
+            // small jobs share launches; large jobs fill it with few slots
+            const bool grow = !S->cfg.baseline && S->cfg.max_slots <= 0;
             for (auto it = S->queue.begin(); it != S->queue.end();) {
                 Job* J = S->jobs[*it].get();
                 if (J->cancel) {
@@ -837,13 +850,17 @@ static void scheduler(gc_server* S) {
                     S->cv.notify_all();
                     continue;
                 }
-                if ((int)S->resident.size() >= slots) break;
+                if ((int)S->resident.size() >= slots &&
+                    !(grow && (int)S->resident.size() < kMaxSlotsSmall &&
+                      S->resident_lanes + J->lanes <= kFillLanes))
+                    break;
                 if (S->used + J->footprint > S->cfg.hbm_budget) {
                     if (S->cfg.baseline) break;
                     ++it;   // a later, smaller job may fit
                     continue;
                 }
                 S->used += J->footprint;
+                S->resident_lanes += J->lanes;
                 S->resident.push_back(J);
                 J->state = GC_JOB_RUNNING;
                 admit.push_back(J);
@@ -1048,6 +1065,9 @@ int gc_submit(gc_server* S, const gc_job* job, uint64_t* job_id) {
         }
         const int64_t n = count_mask_host(job->mask, J->G);
         J->footprint = footprint_of(m, *job, J->G, n);
+        J->lanes = n * (job->kind != GC_JOB_MCMC ? 1
+                        : job->mcmc.sampler == GC_SAMPLER_ENSEMBLE ? job->mcmc.n_walkers
+                                                                   : job->n_chains);
         GC_REQUIRE(J->footprint <= S->cfg.hbm_budget, GC_E_NOMEM,
                    "job needs %zu bytes, budget %zu", J->footprint, S->cfg.hbm_budget);
         std::lock_guard<std::mutex> lk(S->mu);
