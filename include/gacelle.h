@@ -510,6 +510,7 @@ typedef struct {
     double voxel_iters;        /* completed voxel(-chain)-iterations */
     double busy_seconds;       /* wall time with at least one job resident */
     double p50_latency_s, p99_latency_s;   /* submit -> result on host */
+    int peak_resident;         /* most jobs resident at once so far */
 } gc_stats;
 
 int gc_server_create(const gc_server_cfg *cfg, gc_server **out);

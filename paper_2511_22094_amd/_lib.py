@@ -143,7 +143,7 @@ class gc_stats(ctypes.Structure):
                 ("cancelled", c_uint64), ("resident", c_int), ("queued", c_int),
                 ("hbm_in_use", c_size_t), ("voxel_iters", c_double),
                 ("busy_seconds", c_double), ("p50_latency_s", c_double),
-                ("p99_latency_s", c_double)]
+                ("p99_latency_s", c_double), ("peak_resident", c_int)]
 
 
 P = c_void_p

@@ -134,6 +134,7 @@ struct gc_server {
     std::vector<gc::Job*> resident;
     size_t used = 0;
     int64_t resident_lanes = 0;   // lanes of the resident jobs
+    int peak_resident = 0;
     hipStream_t prep = nullptr, compute = nullptr, copy = nullptr;
     // launch lanes of a round (batched mode): the groups of a round run on
     // these streams side by side, fenced by `lane_start` (after the round's
@@ -861,6 +862,7 @@ static void scheduler(gc_server* S) {
                 }
                 S->used += J->footprint;
                 S->resident_lanes += J->lanes;
+                S->peak_resident = std::max(S->peak_resident, (int)S->resident.size() + 1);
                 S->resident.push_back(J);
                 J->state = GC_JOB_RUNNING;
                 admit.push_back(J);
@@ -1158,6 +1160,7 @@ int gc_server_stats(gc_server* S, gc_stats* st) {
     st->busy_seconds = S->busy + (S->busy_since >= 0 ? now_seconds() - S->busy_since : 0.0);
     st->p50_latency_s = percentile(S->latencies, 0.50);
     st->p99_latency_s = percentile(S->latencies, 0.99);
+    st->peak_resident = S->peak_resident;
     return GC_OK;
 }
 

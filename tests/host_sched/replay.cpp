@@ -286,9 +286,9 @@ int main(int argc, char** argv) {
     for (auto& kv : models) gc_model_destroy(kv.second.m);
     const size_t nv = hh::violations();
     std::printf("replay: %zu jobs, %d done (%d before their cancel), %d cancelled, %d failed, "
-                "%d refused; resident %d, in use %zu B after; %.2f s; violations %zu\n",
+                "%d refused; resident %d (peak %d), in use %zu B after; %.2f s; violations %zu\n",
                 trace.size(), done, late_done, canc, failed, refused, stt.resident,
-                stt.hbm_in_use, span, nv);
+                stt.peak_resident, stt.hbm_in_use, span, nv);
     // with an injected launch failure the jobs of that round fail (once their
     // earlier rounds have drained); every job still ends
     const bool ok = nv == 0 && (expect_failures ? failed > 0 : failed == 0) && refused == 0 &&

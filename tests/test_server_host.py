@@ -51,7 +51,8 @@ def harness(tmp_path_factory):
         objs = list(ex.map(lambda s: _compile(s, str(d / (os.path.basename(s) + ".o"))), SOURCES))
     exe = _link(objs, str(d / "replay"))
     for name, nj, vr, mi in (("trace64", 64, (1e3, 1e5), (1000, 4000)),
-                             ("trace256", 256, (1e3, 1e6), (1000, 10000))):
+                             ("trace256", 256, (1e3, 1e6), (1000, 10000)),
+                             ("trace256small", 256, (1e2, 1e4), (1000, 10000))):
         with open(d / f"{name}.txt", "w") as f:
             for j in synth.serving_trace(3, nj, 20.0, vr, mi, (200, 500)):
                 f.write(f"{j.arrival_s:.6f} {j.model} {j.kind} {j.n_vox} {j.seed} "
@@ -161,3 +162,27 @@ def test_replay_detects_lanes_not_joined_into_the_round(harness):
                    "                (void)S->lane_end[k];")
     rc, out = _replay(exe, d / "trace64.txt", "--saturated", delay=300)
     assert rc != 0 and "VIOLATION" in out, out[-3000:]
+
+
+def _peak(out):
+    import re
+    m = re.search(r"resident \d+ \(peak (\d+)\)", out)
+    assert m, out[-2000:]
+    return int(m.group(1))
+
+
+def test_default_admission_takes_many_small_jobs_and_few_large(harness):
+    """With the default slot count, a saturated trace of small jobs keeps more
+    than 64 jobs resident (they hold too few lanes to fill the GPU), an
+    explicit slot count stays a hard limit, and a trace of large jobs stays
+    at 64."""
+    d, exe, _ = harness
+    rc, out = _replay(exe, d / "trace256small.txt", "--saturated", delay=20)
+    assert rc == 0 and "violations 0" in out, out[-6000:]
+    assert _peak(out) > 64, out[-2000:]
+    rc, out = _replay(exe, d / "trace256small.txt", "--saturated", "--slots", "64", delay=20)
+    assert rc == 0 and "violations 0" in out, out[-6000:]
+    assert _peak(out) <= 64, out[-2000:]
+    rc, out = _replay(exe, d / "trace256.txt", "--saturated", delay=20)
+    assert rc == 0 and "violations 0" in out, out[-6000:]
+    assert _peak(out) <= 64, out[-2000:]
