@@ -73,23 +73,23 @@ MH_GRE3_MIX_CEILING = FLOP_PER_MH_STEP_GRE3 * 64 / MH_GRE3_ISSUE_CYCLES / 64.0  
 MEASURED_TRAFFIC = {
     "mh_chunk_cfg4": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
         "sha256": "2a7f2115f4d2c0ea4d0fcb1baad656a7b299c2fb36fb568ecbb15fb0b7d02884",
-        "read_bytes": 3767455737, "write_bytes": 1804631552,
+        "read_bytes": 3767459368, "write_bytes": 1804631552,
         "profile": "profiles/mh_chunk_gre3_240x240x180_ellipsoid_8chains.md"},
     "mh_chunk_cfg1": {"sources": ["gc_mh.hip", "gc_device.hpp", "gc_internal.hpp"],
         "sha256": "2a7f2115f4d2c0ea4d0fcb1baad656a7b299c2fb36fb568ecbb15fb0b7d02884",
-        "read_bytes": 1595955267, "write_bytes": 788529152,
+        "read_bytes": 1595956635, "write_bytes": 788529152,
         "profile": "profiles/mh_chunk_gre3_128x128x64_4chains.md"},
     "fit_step": {"sources": ["gc_fit.hip", "gc_device.hpp", "gc_internal.hpp"],
         "sha256": "430c4e215241d2ba3f0aeb73ce47ba6e06325f97500fcb6505679a7638c8740a",
-        "read_bytes": 126864807, "write_bytes": 15728648,
+        "read_bytes": 126856489, "write_bytes": 15728648,
         "profile": "profiles/fit_step_dwi2_64cubed_adam_tv.md"},
     "sense_ycols": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "bf4c0b2ed8c014624300b12489feae0eeca93feb0dd54b266e6e9c2b0560f476",
-        "read_bytes": 112252793, "write_bytes": 100663321,
+        "sha256": "4e8069406a18d2a669c4aa5424304a68ce821adc1e2ca5fece005d925b77ccaa",
+        "read_bytes": 112252034, "write_bytes": 100663321,
         "profile": "profiles/sense_ycols_6x32_256x256.md"},
     "sense_zrows": {"sources": ["gc_sense.hip", "gc_fft.hpp", "gc_sense.hpp", "gc_device.hpp", "gc_internal.hpp"],
-        "sha256": "bf4c0b2ed8c014624300b12489feae0eeca93feb0dd54b266e6e9c2b0560f476",
-        "read_bytes": 147625970, "write_bytes": 111472116,
+        "sha256": "4e8069406a18d2a669c4aa5424304a68ce821adc1e2ca5fece005d925b77ccaa",
+        "read_bytes": 145928149, "write_bytes": 109899252,
         "profile": "profiles/sense_zrows_6x32_256x256.md"},
 }
 

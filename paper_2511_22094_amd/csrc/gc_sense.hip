@@ -73,9 +73,9 @@ template <int LOG> struct YGeo {
 };
 // z pass geometry: TEAMS coil rows at a time, a team of N2 threads per row.
 // 256-point rows take 8 teams, not 16: a block's LDS is then 21 KB instead of
-// 39 KB, 7 blocks share a CU instead of 4, and the 1,536 blocks of a 6-echo
-// 256-row slice run in one round instead of 1.5 (measured 43.8 -> 42.0 us
-// per pass; 4 teams, 49.7 us).
+// 39 KB, LDS no longer limits a CU to 4 blocks, and the 1,536 blocks of a
+// 6-echo 256-row slice run in one round instead of 1.5 (measured 43.8 -> 42.0
+// us per pass; 4 teams, 49.7 us).
 template <int LOG> struct ZGeo {
     using Sh = FftShape<LOG>;
     static constexpr int T1 = 256 / Sh::N2, T2 = LOG == 8 ? 8 : (4096 >> LOG);
@@ -191,10 +191,12 @@ __global__ __launch_bounds__(256) void sense_ycols_kernel(SenseDev S, const floa
 //         with fwd, the next iteration's forward rows into buf)
 // MODE 1: operator head (forward rows of img_in into buf)
 // MODE 2: adjoint tail (sum over coils of conj(C_c) F_z^H(buf), to out)
-// 256-point rows run best at 4 waves per SIMD (measured; 8 bytes of spill);
-// other lengths keep the registers the compiler wants.
+// The kernel keeps the registers the compiler wants: for 256-point rows 136
+// VGPRs, 3 waves per SIMD, which with 8 teams still holds a 6-echo slice's
+// 1,536 blocks at once (capped at 4 waves per SIMD it spilled and measured
+// slower: 42.1 against 40.3 us per pass).
 template <int LOGZ, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LOGZ == 8 ? 4 : 1)))
+__global__ __launch_bounds__(256)
 void sense_zrows_kernel(SenseDev S, SenseOpt O,
                                                          const float2* __restrict__ img_in,
                                                          float2* __restrict__ img_out,
