@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 # (E, Nc, Ny, Nz)
 SHAPES = [(2, 3, 32, 16), (1, 2, 2, 16), (3, 4, 64, 32), (1, 2, 1024, 16), (1, 1, 16, 1024),
-          (2, 2, 512, 64), (2, 20, 64, 256)]   # last: a second, partial batch of coil rows
+          (2, 2, 512, 64), (2, 20, 64, 256)]   # last: 20 coils leave a partial last batch of coil rows
 
 
 def _draw(shape, seed, sigma=0.01):
