@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 
 # (E, Nc, Ny, Nz)
 SHAPES = [(2, 3, 32, 16), (1, 2, 2, 16), (3, 4, 64, 32), (1, 2, 1024, 16), (1, 1, 16, 1024),
-          (2, 2, 512, 64), (2, 20, 64, 256)]   # last: 20 coils leave a partial last batch of coil rows
+          (2, 2, 512, 64), (2, 20, 64, 256),   # 20 coils leave a partial last batch of coil rows
+          (1, 1, 32, 256), (1, 8, 16, 256)]    # one coil: one live row per batch; 8: one full batch
 
 
 def _draw(shape, seed, sigma=0.01):
