@@ -89,7 +89,7 @@ def test_full_slice_operators_match_oracle():
 
 
 @pytest.mark.parametrize("loss,lam", [(2, 0.0), (1, 0.0), (2, 0.5), (1, 0.5)])
-@pytest.mark.parametrize("shape", [(2, 3, 32, 16), (1, 2, 512, 64), (2, 20, 32, 256)])
+@pytest.mark.parametrize("shape", [(2, 3, 32, 16), (1, 2, 512, 64), (2, 20, 32, 256), (1, 3, 16, 256)])
 def test_one_step_gradient_matches_oracle(loss, lam, shape):
     """SGDM with momentum 0: (init - image) / lr = dL/dRe + i dL/dIm, and the
     recorded loss is the loss at init.  The rate makes lr |g| about 100 |init|
